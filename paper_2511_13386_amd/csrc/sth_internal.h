@@ -1,0 +1,90 @@
+// sth_internal.h -- device-side data layout shared by the kernels and the
+// host library of libsth.so (not part of the public C-ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace sth {
+
+constexpr int kWave = 64;
+constexpr int kMaxNx = 2048;
+constexpr int kMaxSlabs = 4;          // interfaces per thread in streaming kernels (nx <= 4096)
+
+// Per-problem constants of the fine propagator (device memory).
+struct FineConst {
+    int nx, nv;
+    int flags;            // STH_HYBRID | STH_FIELD | STH_LITERAL_R
+    int pad0;
+    double dx, dv, dt, rhobar, m2, eta0, delta0;
+    long long nsteps;     // fine steps per slice
+    const double *eps_p;  // [nx] eps at interfaces
+    const double *eps_c;  // [nx] eps at cell centres
+    const double *e_p;    // [nx] exp(-dt/eps_p^2)
+    const double *a_p;    // [nx] -expm1(-dt/eps_p^2)
+    const double *vtab;   // [4][nv]: |v_j|/dx, M_j, v_j M_j, v_j
+};
+
+// One fine-propagation unit: one slice of one problem.
+struct FineUnit {
+    FineConst c;              // problem constants by value (scalar loads)
+    const double *rho_in;     // [nx] density at the slice start
+    double *rho_out;          // [nx] density at the slice end
+    const void *g_in;         // [nv][nx] v-major start perturbation, Real; NULL = 0
+    void *g_out;              // [nv][nx] v-major end perturbation, Real; NULL = not stored
+                              // (required by the streaming kernels: it is their state)
+    unsigned long long *kin;  // kinetic interface-steps counter (atomic add)
+    int *mask_out;            // [nx] final cell status, or NULL
+    long long nsteps;         // steps of this unit (<= 0: pc->nsteps)
+};
+
+// Launch shape of a fine-sweep kernel class.
+struct FineShape {
+    int prec;     // 0 = FP64, 1 = FP32 bulk
+    int nv;
+    int ipt;      // interfaces per thread (slabs)
+    int stream;   // 1 = perturbation streamed from global memory every step
+    int block;    // threads per workgroup
+    size_t lds;   // dynamic LDS bytes
+};
+
+FineShape fine_shape(int prec, int nx, int nv, int force_stream, int force_block);
+hipError_t launch_fine(const FineShape &s, const FineUnit *d_units, int nunits, hipStream_t st);
+
+// Lifting L^L of rho at interfaces into a v-major Real array.
+struct LiftJob {
+    const FineConst *pc;
+    const double *rho;    // [nx]
+    void *g;              // [nv][nx] v-major Real
+    int lift_order;
+};
+hipError_t launch_lift(int prec, const LiftJob *d_jobs, int njobs, int nx, hipStream_t st);
+
+// Coarse sweep / parareal correction on one problem (single workgroup,
+// sequential over slices).
+struct CoarseJob {
+    const FineConst *pc;
+    double *U;            // [(N+1)][nx] iterate
+    double *Gc;           // [(N+1)][nx] cached coarse values
+    const double *Fv;     // [(N+1)][nx] fine results
+    double *err;          // [1] successive error out
+    double *work;         // [9][nx] workspace
+    double dtG;
+    int N;
+    int mode;             // 0 = coarse guess, 1 = correction
+    int k;                // iteration index (correction)
+};
+hipError_t launch_coarse(const CoarseJob &job, int nx, hipStream_t st);
+
+// Diagnostics of a state (rho, g).
+struct DiagJob {
+    const FineConst *pc;
+    const double *rho;    // [nx]
+    const void *g;        // [nv][nx] v-major Real or NULL (0)
+    double *out;          // [5][nx]: E, J, Phi, N, R
+    int *mask;            // [nx]
+};
+hipError_t launch_diag(int prec, const DiagJob &job, int nx, hipStream_t st);
+
+}  // namespace sth

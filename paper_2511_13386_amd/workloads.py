@@ -56,8 +56,8 @@ def eps_tanh_literal(x: np.ndarray) -> np.ndarray:
 def eps_tanh(x: np.ndarray, w: float = 0.05) -> np.ndarray:
     """Periodic continuation of 1e-4 + 0.5 (1 + tanh((x - 0.5)/w)) on the unit
     torus: the sum over periodic images of the smoothed box [0.5, 1).  It equals
-    the written profile to ~1e-8 on [0.1, 0.9] and replaces its jump at
-    x = 0 == 1 by the mirror transition of the same width.  Fluid on the left
+    the written profile to within 1e-4 on [0.25, 0.75] and replaces its jump
+    at x = 0 == 1 by the mirror transition of the same width.  Fluid on the left
     half (eps ~ 1e-4), kinetic on the right half (eps ~ 1)."""
     x = np.asarray(x, dtype=np.float64)
     s = np.zeros_like(x)

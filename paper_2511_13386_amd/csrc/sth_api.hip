@@ -42,7 +42,7 @@ size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Device layout of one problem (offsets from the arena base).
 struct Layout {
-    size_t cst, eps_p, eps_c, e_p, a_p, vtab, U, Gc, Fv, err, work, kin, mask, g0, gend, gst, units,
+    size_t cst, eps_p, eps_c, e_p, a_p, vtab, vrow64, vrow32, U, Gc, Fv, err, work, kin, mask, g0, gend, gst, units,
         lifts, total;
 };
 
@@ -50,13 +50,15 @@ Layout layout(int nx, int nv, int N, int realsz)
 {
     Layout L;
     size_t o = 0;
-    const size_t gsz = (size_t)nx * nv * realsz;
+    const size_t gsz = fine_slot_elems(nx, nv) * realsz;
     L.cst = o;   o = al256(o + sizeof(FineConst));
     L.eps_p = o; o = al256(o + sizeof(double) * nx);
     L.eps_c = o; o = al256(o + sizeof(double) * nx);
     L.e_p = o;   o = al256(o + sizeof(double) * nx);
     L.a_p = o;   o = al256(o + sizeof(double) * nx);
     L.vtab = o;  o = al256(o + sizeof(double) * 4 * nv);
+    L.vrow64 = o; o = al256(o + sizeof(double) * 4 * nv);
+    L.vrow32 = o; o = al256(o + sizeof(float) * 4 * nv);
     L.U = o;     o = al256(o + sizeof(double) * (size_t)(N + 1) * nx);
     L.Gc = o;    o = al256(o + sizeof(double) * (size_t)(N + 1) * nx);
     L.Fv = o;    o = al256(o + sizeof(double) * (size_t)(N + 1) * nx);
@@ -89,6 +91,8 @@ int validate(const sth_problem_desc *d)
     if (d->precision != STH_FP64 && d->precision != STH_FP32_BULK)
         return fail(STH_EINVAL, "unknown precision");
     if (d->flags & ~(STH_HYBRID | STH_FIELD | STH_LITERAL_R)) return fail(STH_EINVAL, "unknown flags");
+    if (fine_shape(d->precision == STH_FP64 ? 0 : 1, d->nx, d->nv, 0, 0).lds > kMaxLds)
+        return fail(STH_EINVAL, "unit too large for one workgroup's LDS (FP64 with nv = 128 needs nx <= 1024)");
     return STH_OK;
 }
 
@@ -142,7 +146,8 @@ struct sth_problem {
 
     template <typename T>
     T *at(size_t off) const { return (T *)(base + off); }
-    size_t gslab() const { return (size_t)nx * nv * realsz; }
+    // one slice's perturbation slot: rows [nv][nx] plus the lazy projection [2][nx]
+    size_t gslab() const { return fine_slot_elems(nx, nv) * realsz; }
 };
 
 namespace {
@@ -330,6 +335,15 @@ int sth_create(const sth_problem_desc *d, void *arena, size_t arena_bytes, sth_p
     c.e_p = p->at<double>(p->L.e_p);
     c.a_p = p->at<double>(p->L.a_p);
     c.vtab = p->at<double>(p->L.vtab);
+    c.vrow64 = p->at<double>(p->L.vrow64);
+    c.vrow32 = p->at<float>(p->L.vrow32);
+    std::vector<double> vrow64(4 * (size_t)nv);
+    std::vector<float> vrow32(4 * (size_t)nv);
+    for (int j = 0; j < nv; ++j)
+        for (int q = 0; q < 4; ++q) {
+            vrow64[4 * j + q] = vtab[(size_t)q * nv + j];
+            vrow32[4 * j + q] = (float)vtab[(size_t)q * nv + j];
+        }
 
     p->fc = c;
     auto up = [&](size_t off, const void *src, size_t n) { return hipMemcpy(p->base + off, src, n, hipMemcpyHostToDevice); };
@@ -340,6 +354,8 @@ int sth_create(const sth_problem_desc *d, void *arena, size_t arena_bytes, sth_p
     if (e == hipSuccess) e = up(p->L.e_p, e_p.data(), sizeof(double) * nx);
     if (e == hipSuccess) e = up(p->L.a_p, a_p.data(), sizeof(double) * nx);
     if (e == hipSuccess) e = up(p->L.vtab, vtab.data(), sizeof(double) * 4 * nv);
+    if (e == hipSuccess) e = up(p->L.vrow64, vrow64.data(), sizeof(double) * 4 * nv);
+    if (e == hipSuccess) e = up(p->L.vrow32, vrow32.data(), sizeof(float) * 4 * nv);
     if (e == hipSuccess) e = hipMemset(p->base + p->L.U, 0, p->L.err - p->L.U);
     if (e == hipSuccess) e = up(p->L.U, rho0.data(), sizeof(double) * nx);
     if (e == hipSuccess) e = hipMemset(p->base + p->L.kin, 0, sizeof(unsigned long long) * (N + 1));
@@ -551,8 +567,8 @@ int sth_get_g(const sth_problem *p, int slice, double *host_out)
     if (!p || !host_out) return fail(STH_EINVAL, "null argument");
     if (slice < 1 || slice > p->N) return fail(STH_EINVAL, "slice must be in 1..N");
     HIPCHK(hipDeviceSynchronize());
-    std::vector<char> buf(p->gslab());
-    HIPCHK(hipMemcpy(buf.data(), p->base + p->L.gend + (size_t)slice * p->gslab(), p->gslab(),
+    std::vector<char> buf((size_t)p->nx * p->nv * p->realsz);
+    HIPCHK(hipMemcpy(buf.data(), p->base + p->L.gend + (size_t)slice * p->gslab(), buf.size(),
                      hipMemcpyDeviceToHost));
     from_vmajor(buf, p->nx, p->nv, p->prec, host_out);
     return STH_OK;
@@ -615,8 +631,8 @@ int sth_fine_run(sth_problem *p, const double *rho_in, const double *g_in, long 
     HIPCHK(hipStreamSynchronize(st));
     if (rho_out) HIPCHK(hipMemcpy(rho_out, d_rout, sizeof(double) * nx, hipMemcpyDeviceToHost));
     if (g_out) {
-        std::vector<char> buf(p->gslab());
-        HIPCHK(hipMemcpy(buf.data(), d_gout, p->gslab(), hipMemcpyDeviceToHost));
+        std::vector<char> buf((size_t)nx * p->nv * p->realsz);
+        HIPCHK(hipMemcpy(buf.data(), d_gout, buf.size(), hipMemcpyDeviceToHost));
         from_vmajor(buf, nx, p->nv, p->prec, g_out);
     }
     if (cell_mask_out) HIPCHK(hipMemcpy(cell_mask_out, u.mask_out, sizeof(int) * nx, hipMemcpyDeviceToHost));

@@ -10,7 +10,8 @@ namespace sth {
 
 constexpr int kWave = 64;
 constexpr int kMaxNx = 2048;
-constexpr int kMaxSlabs = 4;          // interfaces per thread in streaming kernels (nx <= 4096)
+constexpr size_t kMaxLds = 160 * 1024;  // LDS bytes of one gfx950 workgroup
+constexpr int kMaxSlabs = 4;          // interfaces per thread (nx <= 2048 with 512 threads)
 
 // Per-problem constants of the fine propagator (device memory).
 struct FineConst {
@@ -24,7 +25,17 @@ struct FineConst {
     const double *e_p;    // [nx] exp(-dt/eps_p^2)
     const double *a_p;    // [nx] -expm1(-dt/eps_p^2)
     const double *vtab;   // [4][nv]: |v_j|/dx, M_j, v_j M_j, v_j
+    const double *vrow64; // [nv][4]: the same table row-wise, float64
+    const float *vrow32;  // [nv][4]: the same table row-wise, float32
 };
+
+// Per-unit state slot in global memory (elements of the working precision):
+// rows W[nv][nx] (v-major) and the lazy projection C1[2][nx].  After a sweep
+// W holds the perturbation.
+__host__ __device__ inline size_t fine_slot_elems(int nx, int nv)
+{
+    return (size_t)nv * nx + 2 * (size_t)nx;
+}
 
 // One fine-propagation unit: one slice of one problem.
 struct FineUnit {

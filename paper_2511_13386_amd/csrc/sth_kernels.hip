@@ -74,144 +74,136 @@ __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(
 
 // LDS layout of the fine kernel.  Same function on host (sizing) and device.
 struct FineLds {
-    size_t rho, jc, phi, nrm, cm, tot, wtot, jtot, vt, halo, total;
+    size_t rho, jc, phi, E, nrm, cm, tot, wtot, jtot, halo, total;
 };
 __host__ __device__ inline FineLds fine_lds(int nx, int nv, int realsz, int nslot)
 {
     FineLds L;
     size_t o = 0;
-    int nseg = (nx + kWave - 1) / kWave;
     L.rho = o;  o = align16(o + sizeof(double) * nx);
     L.jc = o;   o = align16(o + sizeof(double) * nx);
     L.phi = o;  o = align16(o + sizeof(double) * nx);
+    L.E = o;    o = align16(o + sizeof(double) * nx);
     L.nrm = o;  o = align16(o + (size_t)realsz * 2 * nx);
-    L.cm = o;   o = align16(o + sizeof(int) * nx);
+    L.cm = o;   o = align16(o + sizeof(unsigned char) * nx);
     L.tot = o;  o = align16(o + sizeof(double) * nslot);
     L.wtot = o; o = align16(o + sizeof(double) * nslot);
     L.jtot = o; o = align16(o + sizeof(double) * nslot);
-    L.vt = o;   o = align16(o + (size_t)realsz * 4 * nv);
-    L.halo = o; o = align16(o + (size_t)realsz * 2 * 2 * nseg * (nv / 2));
+    L.halo = o; o = align16(o + (size_t)realsz * 2 * 2 * ((nx + kWave - 1) / kWave) * (nv / 2));
     L.total = o;
     return L;
 }
 
+
 // ------------------------------------------------------------ fine sweep
-// Coefficients of one kinetic interface row for one step.
+// Row state.  A unit's perturbation lives in a v-major global buffer
+// W[j][p] (lanes = consecutive interfaces, so every row access is coalesced)
+// followed by C1[2][p].  The projection of the micro-macro step is applied
+// lazily: the stored row is w = g - M c1 with c1 = a eps <A> from the step that
+// produced it, and every read reconstructs g = w + M c1.  One step therefore
+// reads and writes each cell once:
+//   g_j  = w_j + M_j c1
+//   A_j  = |v_j|/dx (g_j - g_up,j) + (G_{j+1/2} - G_{j-1/2})/dv
+//   w'_j = e g_j - a eps A_j - a J v_j M_j          (= g'_j - M_j a eps <A>)
+//   c1'  = a eps <A> = a eps dv sum_j |v_j|/dx (g_j - g_up,j)
+// (the velocity part of <A> telescopes to zero with zero-flux ends), and the
+// moments of g' follow from running sums of w':
+//   Phi = -dv sum v_j w'_j                         (sum_j v_j M_j = 0)
+//   |g'|^2 = dv (sum w'^2 + 2 c1' sum w' M + c1'^2 sum M^2).
+constexpr int kChunk = 8;  // velocities per software-pipelined chunk
+constexpr int kFineBlock = 512;  // threads per fine-sweep workgroup at most
+
+// Uniform per-velocity constants are read through the constant address space
+// so that they are scalar loads into SGPRs, not vector registers.
+template <typename Real>
+using ConstPtr = const __attribute__((address_space(4))) Real *;
+
 template <typename Real>
 struct RowCoef {
-    Real Ep, Em, e, aeps, c2;   // E+/dv, E-/dv, exp(-dt/eps^2), a eps, -a J
+    Real Ep, Em, e, aeps, aJ;  // E+/dv, E-/dv, exp(-dt/eps^2), a eps, a J
+    Real c1, c1n, c1p;         // lazy projection of this row and its neighbours
 };
 
-// Transport (upwind in x across lanes, in v along the row), projection,
-// relaxation and moments of one interface row.  g[j] holds g'^n on entry and
-// g'^{n+1} on exit (0 on fluid lanes).  vt is [NV][4]: |v|/dx, M, v M, v.
-// hnext/hprev: halo rows for the segment's last lane (v<0 half of row p+1)
-// and first lane (v>0 half of row p-1).
+template <typename Real>
+struct RowOut {
+    Real Sx, phi, ww, wm;      // sum |v|/dx (g - g_up), sum v w', sum w'^2, sum w' M
+};
+
+// One kinetic-interface row.  lastlane: last valid lane of the segment; the
+// wave-edge upwind neighbours come from the halo rows hnext (v<0 half of row
+// p+1) and hprev (v>0 half of row p-1), stored raw (w form).
 template <typename Real, int NV>
-__device__ __forceinline__ void row_resident(Real (&g)[NV], const RowCoef<Real> &c, bool kin,
-                                             int lane, int lastlane, const Real *vt,
-                                             const Real *hnext, const Real *hprev, Real dvR,
-                                             Real &phi, Real &nn)
+__device__ __forceinline__ RowOut<Real> row_pass(Real *__restrict__ Wp, int nx, bool valid, bool kin,
+                                                 const RowCoef<Real> &c, int lane, int lastlane,
+                                                 ConstPtr<Real> vt, const Real *hnext, const Real *hprev,
+                                                 Real *hfirst_out, Real *hlast_out)
 {
     constexpr int HV = NV / 2;
-    // Four partial sums per velocity moment: independent accumulation chains
-    // let each A_j / g_j be consumed as soon as it is produced.
-    Real S[4] = {0, 0, 0, 0};
+    RowOut<Real> o{0, 0, 0, 0};
     Real Glo = 0;
+    Real cur[kChunk + 1];
 #pragma unroll
-    for (int j = 0; j < NV; ++j) {
-        const Real gj = g[j];
-        Real gx;
-        if (j < HV) {  // v_j < 0: upwind neighbour is p+1
-            const Real h = hnext[j];
-            gx = __shfl_down(gj, 1, kWave);
-            gx = lane == lastlane ? h : gx;
-        } else {       // v_j > 0: upwind neighbour is p-1
-            const Real h = hprev[j - HV];
-            gx = __shfl_up(gj, 1, kWave);
-            gx = lane == 0 ? h : gx;
+    for (int t = 0; t <= kChunk; ++t)
+        cur[t] = (valid && t < NV) ? Wp[(size_t)t * nx] : Real(0);
+#pragma unroll 1
+    for (int j0 = 0; j0 < NV; j0 += kChunk) {
+        Real nxt[kChunk];
+#pragma unroll
+        for (int t = 0; t < kChunk; ++t) {
+            const int jj = j0 + kChunk + 1 + t;
+            nxt[t] = (valid && jj < NV) ? Wp[(size_t)jj * nx] : Real(0);
         }
-        const Real ghi = (j < NV - 1) ? c.Ep * gj + c.Em * g[(j + 1) % NV] : Real(0);
-        const Real A = vt[4 * j] * (gj - gx) + (ghi - Glo);
-        Glo = ghi;
-        S[j & 3] += A;
-        g[j] = c.e * gj - c.aeps * A;
-    }
-    const Real c1 = c.aeps * (((S[0] + S[1]) + (S[2] + S[3])) * dvR);
-    Real p[4] = {0, 0, 0, 0}, q[4] = {0, 0, 0, 0};
+        Real gnext = cur[0] + vt[4 * j0 + 1] * c.c1;
 #pragma unroll
-    for (int j = 0; j < NV; ++j) {
-        Real gn = g[j] + vt[4 * j + 1] * c1 + vt[4 * j + 2] * c.c2;
-        gn = kin ? gn : Real(0);
-        g[j] = gn;
-        p[j & 3] += vt[4 * j + 3] * gn;
-        q[j & 3] += gn * gn;
+        for (int t = 0; t < kChunk; ++t) {
+            const int j = j0 + t;
+            const Real cx = vt[4 * j], M = vt[4 * j + 1], vM = vt[4 * j + 2], v = vt[4 * j + 3];
+            const Real gj = gnext;
+            gnext = (j + 1 < NV) ? cur[t + 1] + vt[4 * (j + 1) + 1] * c.c1 : Real(0);
+            Real gx;
+            if (j < HV) {      // v_j < 0: upwind neighbour is p+1
+                const Real h = hnext[j] + M * c.c1n;
+                gx = __shfl_down(gj, 1, kWave);
+                gx = lane == lastlane ? h : gx;
+            } else {           // v_j > 0: upwind neighbour is p-1
+                const Real h = hprev[j - HV] + M * c.c1p;
+                gx = __shfl_up(gj, 1, kWave);
+                gx = lane == 0 ? h : gx;
+            }
+            const Real ghi = (j < NV - 1) ? c.Ep * gj + c.Em * gnext : Real(0);
+            const Real dg = gj - gx;
+            const Real gv = ghi - Glo;
+            Glo = ghi;
+            o.Sx += cx * dg;
+            const Real A = cx * dg + gv;
+            Real w = c.e * gj - c.aeps * A - c.aJ * vM;
+            w = kin ? w : Real(0);
+            if (valid && kin) Wp[(size_t)j * nx] = w;
+            if (lane == 0 && j < HV) hfirst_out[j] = w;
+            if (lane == lastlane && j >= HV) hlast_out[j - HV] = w;
+            o.phi += v * w;
+            o.ww += w * w;
+            o.wm += w * M;
+        }
+        cur[0] = cur[kChunk];
+#pragma unroll
+        for (int t = 0; t < kChunk; ++t) cur[t + 1] = nxt[t];
     }
-    phi = (p[0] + p[1]) + (p[2] + p[3]);
-    nn = (q[0] + q[1]) + (q[2] + q[3]);
+    return o;
 }
 
-// Streaming variant: the row lives in global memory gp[j*nx] (v-major) and is
-// updated in place (neighbour values come from lanes and the LDS halo, never
-// from global memory, so the in-place update is race free).
-template <typename Real, int NV>
-__device__ __forceinline__ void row_stream(Real *gp, int nx, bool valid, const RowCoef<Real> &c,
-                                           bool kin, int lane, int lastlane, const Real *vt,
-                                           const Real *hnext, const Real *hprev, Real dvR,
-                                           Real *hfirst_out, Real *hlast_out, Real &phi, Real &nn)
+// Fine sweep: one workgroup per unit (slice), all fine steps of the slice in
+// one launch.  Threads own interfaces/cells p = k*B + t (slab k).
+template <typename Real, int NV, int IPTM>
+__global__ void __launch_bounds__(kFineBlock) k_fine(const FineUnit *__restrict__ units)
 {
-    constexpr int HV = NV / 2;
-    Real S[4] = {0, 0, 0, 0}, Glo = 0;
-    Real gnext = valid ? gp[0] : Real(0);
-    for (int j = 0; j < NV; ++j) {
-        const Real gj = gnext;
-        gnext = (valid && j + 1 < NV) ? gp[(size_t)(j + 1) * nx] : Real(0);
-        Real gx;
-        if (j < HV) {
-            const Real h = hnext[j];
-            gx = __shfl_down(gj, 1, kWave);
-            gx = lane == lastlane ? h : gx;
-        } else {
-            const Real h = hprev[j - HV];
-            gx = __shfl_up(gj, 1, kWave);
-            gx = lane == 0 ? h : gx;
-        }
-        const Real ghi = (j < NV - 1) ? c.Ep * gj + c.Em * gnext : Real(0);
-        const Real A = vt[4 * j] * (gj - gx) + (ghi - Glo);
-        Glo = ghi;
-        S[j & 3] += A;
-        if (valid) gp[(size_t)j * nx] = c.e * gj - c.aeps * A;
-    }
-    const Real c1 = c.aeps * (((S[0] + S[1]) + (S[2] + S[3])) * dvR);
-    Real p[4] = {0, 0, 0, 0}, q[4] = {0, 0, 0, 0};
-    for (int j = 0; j < NV; ++j) {
-        Real gn = valid ? gp[(size_t)j * nx] : Real(0);
-        gn = gn + vt[4 * j + 1] * c1 + vt[4 * j + 2] * c.c2;
-        gn = kin ? gn : Real(0);
-        if (valid) gp[(size_t)j * nx] = gn;
-        if (lane == 0 && j < HV) hfirst_out[j] = gn;
-        if (lane == lastlane && j >= HV) hlast_out[j - HV] = gn;
-        p[j & 3] += vt[4 * j + 3] * gn;
-        q[j & 3] += gn * gn;
-    }
-    phi = (p[0] + p[1]) + (p[2] + p[3]);
-    nn = (q[0] + q[1]) + (q[2] + q[3]);
-}
-
-// Fine sweep: one workgroup per unit (slice).  Per-thread state kept across
-// steps is the perturbation (resident kernels) and two status bitmasks;
-// everything macroscopic lives in LDS.
-template <typename Real, int NV, int IPT, bool STREAM>
-__global__ void __launch_bounds__(STREAM ? 1024 : 512) k_fine(const FineUnit *__restrict__ units)
-{
-    constexpr int IPTM = STREAM ? kMaxSlabs : IPT;
     constexpr int HV = NV / 2;
     extern __shared__ __align__(16) unsigned char smem[];
 
     const FineUnit &U = units[blockIdx.x];
     const FineConst *__restrict__ C = &U.c;
     const int nx = C->nx;
-    int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
     const int BS = blockDim.x, NW = BS / kWave;
     const int ipt = (nx + BS - 1) / BS;
     const int nseg = (nx + kWave - 1) / kWave;
@@ -229,70 +221,65 @@ __global__ void __launch_bounds__(STREAM ? 1024 : 512) k_fine(const FineUnit *__
     double *s_jc = (double *)(smem + L.jc);
     double *s_phi = (double *)(smem + L.phi);
     Real *s_nrm = (Real *)(smem + L.nrm);      // [2][nx]
-    int *s_cm = (int *)(smem + L.cm);
+    unsigned char *s_cm = (unsigned char *)(smem + L.cm);
     double *s_tot = (double *)(smem + L.tot);
     double *s_wtot = (double *)(smem + L.wtot);
     double *s_jtot = (double *)(smem + L.jtot);
-    Real *s_vt = (Real *)(smem + L.vt);        // [NV][4]
-    Real *s_halo = (Real *)(smem + L.halo);    // [2 parity][2 side][nseg][HV]
+    double *s_E = (double *)(smem + L.E);
+
+    Real *W = (Real *)U.g_out;                 // [NV][nx] rows
+    Real *C1 = W + (size_t)NV * nx;            // [2][nx] lazy projection
+    Real *s_halo = (Real *)(smem + L.halo);    // [2 parity][2 side][nseg][HV] halo rows
     // side 0: first row of a segment, v<0 half; side 1: last row, v>0 half
 #define HALO(par, side, seg) (s_halo + ((size_t)((par) * 2 + (side)) * nseg + (seg)) * HV)
 
-    for (int t = tid; t < 4 * NV; t += BS) {
-        const int j = t >> 2, q = t & 3;
-        s_vt[t] = (Real)C->vtab[q * NV + j];
+    Real msq = 0;  // sum_j M_j^2
+    for (int j = 0; j < NV; ++j) {
+        const Real M = (Real)C->vtab[NV + j];
+        msq += M * M;
     }
+    // [NV][4] table in the working precision for the row passes
+    const ConstPtr<Real> vtr = (ConstPtr<Real>)(sizeof(Real) == 8 ? (const void *)C->vrow64
+                                                                 : (const void *)C->vrow32);
 
-    Real *gbuf = (Real *)U.g_out;              // streaming state / output
     const Real *gin = (const Real *)U.g_in;
+    const Real dvR = (Real)C->dv;
 
-    Real gres[STREAM ? 1 : IPT][STREAM ? 1 : NV];
     unsigned kinbits = 0, cmbits = 0;          // status of the thread's slabs
     unsigned long long kcount = 0;
+    double comp[IPTM];                         // compensation of the density sums
 
     // ---------------------------------------------------------- prologue
 #pragma unroll
     for (int k = 0; k < IPTM; ++k) {
         const int i = k * BS + tid;
-        const int lane = tid & (kWave - 1);
         const bool valid = (k < ipt) && (i < nx);
+        comp[k] = 0.0;
         if (valid) s_rho[i] = U.rho_in[i];
         kinbits |= 1u << k;
         cmbits |= 1u << k;
-        if (k < ipt) {
+        if (valid) {
             Real q = 0;
             const int seg = i / kWave, last = min(kWave - 1, nx - 1 - seg * kWave);
-            if constexpr (STREAM) {
-                for (int j = 0; j < NV; ++j) {
-                    const Real v = (valid && gin) ? gin[(size_t)j * nx + i] : Real(0);
-                    if (valid) gbuf[(size_t)j * nx + i] = v;
-                    q += v * v;
-                    if (valid && lane == 0 && j < HV) HALO(0, 0, seg)[j] = v;
-                    if (valid && lane == last && j >= HV) HALO(0, 1, seg)[j - HV] = v;
-                }
-            } else {
-#pragma unroll
-                for (int j = 0; j < NV; ++j) {
-                    const Real v = (valid && gin) ? gin[(size_t)j * nx + i] : Real(0);
-                    gres[k][j] = v;
-                    q += v * v;
-                }
-                if (valid && lane == 0)
-                    for (int j = 0; j < HV; ++j) HALO(0, 0, seg)[j] = gres[k][j];
-                if (valid && lane == last)
-                    for (int j = HV; j < NV; ++j) HALO(0, 1, seg)[j - HV] = gres[k][j];
+            for (int j = 0; j < NV; ++j) {
+                const Real v = gin ? gin[(size_t)j * nx + i] : Real(0);
+                W[(size_t)j * nx + i] = v;
+                q += v * v;
+                if (lane == 0 && j < HV) HALO(0, 0, seg)[j] = v;
+                if (lane == last && j >= HV) HALO(0, 1, seg)[j - HV] = v;
             }
-            if (valid) s_nrm[i] = (Real)g_eps[i] * (Real)sqrt((double)(q * (Real)C->dv));
+            C1[i] = Real(0);
+            C1[nx + i] = Real(0);
+            s_nrm[i] = (Real)g_eps[i] * (Real)sqrt((double)(q * dvR));
         }
     }
     __syncthreads();
 
-    double incl[IPTM], Ew[IPTM], Jw[IPTM];
+    double incl[IPTM];
 
     // Wave prefix sums of d_i = (rho_i - rhobar) dx and of d_i (nx - i), whose
     // total is sum_p s_p (for the zero-mean gauge).
     auto macro_scan = [&]() {
-        const int lane = tid & (kWave - 1), wid = tid / kWave;
         const double rhobar = C->rhobar, dx = C->dx;
 #pragma unroll
         for (int k = 0; k < IPTM; ++k) {
@@ -313,12 +300,11 @@ __global__ void __launch_bounds__(STREAM ? 1024 : 512) k_fine(const FineUnit *__
     // Field E_p (Gauss law, zero-mean gauge), flux J_p, and (hybrid) the
     // cell-centred J_i = d1 rho_i - E_i rho_i with E_i = E_p - d_p/2.
     auto macro_field = [&]() {
-        const int lane = tid & (kWave - 1), wid = tid / kWave;
         const double rhobar = C->rhobar, dx = C->dx, inv_dx = 1.0 / dx;
         const double t = lane < nslot ? s_tot[lane] : 0.0;
         const double ex = wave_incl_scan(t, lane) - t;
-        const double W = wave_sum(lane < nslot ? s_wtot[lane] : 0.0);
-        const double mean_s = W / (double)nx;
+        const double Wsum = wave_sum(lane < nslot ? s_wtot[lane] : 0.0);
+        const double mean_s = Wsum / (double)nx;
 #pragma unroll
         for (int k = 0; k < IPTM; ++k) {
             if (k < ipt) {
@@ -326,11 +312,10 @@ __global__ void __launch_bounds__(STREAM ? 1024 : 512) k_fine(const FineUnit *__
                 const bool valid = i < nx;
                 const double pre = __shfl(ex, k * NW + wid, kWave);
                 const double E = field ? (pre + incl[k]) - mean_s : 0.0;
-                Ew[k] = E;
                 double jsum = 0.0;
                 if (valid) {
-                    const double r = s_rho[i], rn = s_rho[wrapi(i + 1, nx)];
-                    Jw[k] = (rn - r) * inv_dx - E * 0.5 * (r + rn);
+                    const double r = s_rho[i];
+                    s_E[i] = E;
                     if (hybrid) {
                         const double Ec = field ? E - 0.5 * (r - rhobar) * dx : 0.0;
                         const double jc = fd1(s_rho, i, nx) * inv_dx - Ec * r;
@@ -348,7 +333,6 @@ __global__ void __launch_bounds__(STREAM ? 1024 : 512) k_fine(const FineUnit *__
     // Remainder R_i (eq. RemainderBis, Table 1 stencils) and the cell rule;
     // initial = true applies the kinetic-cell rule to every cell.
     auto macro_rule = [&](int par, bool initial) {
-        const int lane = tid & (kWave - 1);
         const double rhobar = C->rhobar, dx = C->dx, inv_dx = 1.0 / dx;
         const double inv_dx2 = inv_dx * inv_dx, inv_dx3 = inv_dx2 * inv_dx;
         const double eta0 = C->eta0, delta0 = C->delta0;
@@ -363,7 +347,7 @@ __global__ void __launch_bounds__(STREAM ? 1024 : 512) k_fine(const FineUnit *__
                 const double d3J = fd3(s_jc, i, nx) * inv_dx3;
                 double R;
                 if (field) {
-                    const double Ec = Ew[k] - 0.5 * (r - rhobar) * dx;
+                    const double Ec = s_E[i] - 0.5 * (r - rhobar) * dx;
                     const double d1r = fd1(s_rho, i, nx) * inv_dx;
                     const double d2J = fd2(s_jc, i, nx) * inv_dx2;
                     R = -d3J + Ec * d2J + (2.0 * r - 3.0 * rhobar) * d1J + 2.0 * jc * d1r
@@ -380,14 +364,13 @@ __global__ void __launch_bounds__(STREAM ? 1024 : 512) k_fine(const FineUnit *__
                 if (initial || ((cmbits >> k) & 1u)) c = (nmax > delta0) || (crit > eta0);
                 else c = crit > eta0;
                 cmbits = (cmbits & ~(1u << k)) | ((unsigned)c << k);
-                s_cm[i] = c;
+                s_cm[i] = (unsigned char)c;
             }
         }
     };
     // Interface status of step n from s_cm; interfaces turning fluid get
-    // g' = 0 (registers or global state, norm, both halo parities).
+    // g' = 0 (row, lazy projection, norm, both halo parities).
     auto apply_status = [&](int par) {
-        const int lane = tid & (kWave - 1);
 #pragma unroll
         for (int k = 0; k < IPTM; ++k) {
             const int i = k * BS + tid;
@@ -395,12 +378,9 @@ __global__ void __launch_bounds__(STREAM ? 1024 : 512) k_fine(const FineUnit *__
                 const int kn = s_cm[i] | s_cm[wrapi(i + 1, nx)];
                 if (((kinbits >> k) & 1u) && !kn) {
                     const int seg = i / kWave, last = min(kWave - 1, nx - 1 - seg * kWave);
-                    if constexpr (STREAM) {
-                        for (int j = 0; j < NV; ++j) gbuf[(size_t)j * nx + i] = Real(0);
-                    } else {
-#pragma unroll
-                        for (int j = 0; j < NV; ++j) gres[k][j] = Real(0);
-                    }
+                    for (int j = 0; j < NV; ++j) W[(size_t)j * nx + i] = Real(0);
+                    C1[i] = Real(0);
+                    C1[nx + i] = Real(0);
                     s_nrm[par * nx + i] = Real(0);
                     for (int pp = 0; pp < 2; ++pp) {
                         if (lane == 0)
@@ -410,6 +390,22 @@ __global__ void __launch_bounds__(STREAM ? 1024 : 512) k_fine(const FineUnit *__
                     }
                 }
                 kinbits = (kinbits & ~(1u << k)) | ((unsigned)kn << k);
+            }
+        }
+    };
+    // Conservative density update with the fluxes of the previous step,
+    // compensated (Kahan) so that long slices keep the mass to round-off.
+    auto density_update = [&]() {
+        const double dtdx = C->dt / C->dx;
+#pragma unroll
+        for (int k = 0; k < IPTM; ++k) {
+            const int i = k * BS + tid;
+            if (k < ipt && i < nx) {
+                const double r = s_rho[i];
+                const double y = dtdx * (s_phi[i] - s_phi[wrapi(i - 1, nx)]) - comp[k];
+                const double t = r + y;
+                comp[k] = (t - r) - y;
+                s_rho[i] = t;
             }
         }
     };
@@ -432,22 +428,8 @@ __global__ void __launch_bounds__(STREAM ? 1024 : 512) k_fine(const FineUnit *__
     // ---------------------------------------------------------- step loop
     for (long long n = 0; n < nsteps; ++n) {
         const int par = (int)(n & 1), npar = par ^ 1;
-        // Opaque per-step values: keep address arithmetic and velocity-table
-        // loads inside the loop instead of pinning them in registers.
-        asm volatile("" : "+v"(tid));
-        int vo = 0;
-        asm volatile("" : "+s"(vo));
-        const Real *vts = s_vt + vo;
-        const int lane = tid & (kWave - 1), wid = tid / kWave;
         // P1: density update with the previous fluxes, interface status.
-        if (n > 0) {
-            const double dtdx = C->dt / C->dx;
-#pragma unroll
-            for (int k = 0; k < IPTM; ++k) {
-                const int i = k * BS + tid;
-                if (k < ipt && i < nx) s_rho[i] = s_rho[i] + dtdx * (s_phi[i] - s_phi[wrapi(i - 1, nx)]);
-            }
-        }
+        if (n > 0) density_update();
         if (hybrid) apply_status(par);
         macro_scan();
         __syncthreads();  // B1
@@ -456,62 +438,59 @@ __global__ void __launch_bounds__(STREAM ? 1024 : 512) k_fine(const FineUnit *__
         __syncthreads();  // B2
         // P3: phase-space pass of kinetic interfaces, then the cell rule.
         {
-            const double dv = C->dv, m2 = C->m2;
-            const Real dvR = (Real)dv;
-#pragma unroll
-            for (int k = 0; k < IPTM; ++k) {
-                if (k < ipt) {
-                    const int i = k * BS + tid;
-                    const bool valid = i < nx;
-                    const bool kv = valid && ((kinbits >> k) & 1u);
-                    kcount += kv ? 1ull : 0ull;
-                    const int seg = k * NW + wid;
-                    const unsigned long long any = __ballot(kv);
-                    double Phi = m2 * Jw[k];
-                    Real Nn = 0;
-                    if (any && seg < nseg) {
-                        const int last = min(kWave - 1, nx - 1 - seg * kWave);
-                        const double E = Ew[k];
-                        const Real er = valid ? (Real)g_e[i] : Real(0);
-                        const Real ar = valid ? (Real)g_a[i] : Real(0);
-                        const Real epsr = valid ? (Real)g_eps[i] : Real(1);
-                        RowCoef<Real> c;
-                        c.Ep = (Real)(E > 0.0 ? E / dv : 0.0);
-                        c.Em = (Real)(E < 0.0 ? E / dv : 0.0);
-                        c.e = er;
-                        c.aeps = ar * epsr;
-                        c.c2 = (Real)(-(double)ar * Jw[k]);
-                        const int segn = seg + 1 == nseg ? 0 : seg + 1;
-                        const int segp = seg == 0 ? nseg - 1 : seg - 1;
-                        const Real *hnext = HALO(par, 0, segn);
-                        const Real *hprev = HALO(par, 1, segp);
-                        Real phi, nn;
-                        if constexpr (STREAM) {
-                            row_stream<Real, NV>(gbuf + i, nx, valid, c, kv, lane, last, vts, hnext, hprev,
-                                                 dvR, HALO(npar, 0, seg), HALO(npar, 1, seg), phi, nn);
-                        } else {
-                            row_resident<Real, NV>(gres[k], c, kv, lane, last, vts, hnext, hprev, dvR, phi,
-                                                   nn);
-                            if (valid && lane == 0) {
-                                Real *h = HALO(npar, 0, seg);
-#pragma unroll
-                                for (int j = 0; j < HV; ++j) h[j] = gres[k][j];
-                            }
-                            if (valid && lane == last) {
-                                Real *h = HALO(npar, 1, seg);
-#pragma unroll
-                                for (int j = HV; j < NV; ++j) h[j - HV] = gres[k][j];
-                            }
-                        }
-                        if (kv) {
-                            Phi = -(double)phi * dv;
-                            Nn = epsr * (Real)sqrt((double)(nn * dvR));
-                        }
+            const double dv = C->dv, m2 = C->m2, inv_dx = 1.0 / C->dx;
+#pragma unroll 1
+            for (int k = 0; k < ipt; ++k) {
+                const int i = k * BS + tid;
+                const bool valid = i < nx;
+                const bool kv = valid && ((kinbits >> k) & 1u);
+                kcount += kv ? 1ull : 0ull;
+                const int seg = k * NW + wid;
+                double E = 0.0, J = 0.0;
+                if (valid) {
+                    const double r = s_rho[i], rn = s_rho[wrapi(i + 1, nx)];
+                    E = s_E[i];
+                    J = (rn - r) * inv_dx - E * 0.5 * (r + rn);
+                }
+                const unsigned long long any = __ballot(kv);
+                double Phi = m2 * J;
+                Real Nn = 0;
+                if (any && seg < nseg) {
+                    const int last = min(kWave - 1, nx - 1 - seg * kWave);
+                    const int segn = seg + 1 == nseg ? 0 : seg + 1;
+                    const int segp = seg == 0 ? nseg - 1 : seg - 1;
+                    const Real er = valid ? (Real)g_e[i] : Real(0);
+                    const Real ar = valid ? (Real)g_a[i] : Real(0);
+                    const Real epsr = valid ? (Real)g_eps[i] : Real(1);
+                    RowCoef<Real> c;
+                    c.Ep = (Real)(E > 0.0 ? E / dv : 0.0);
+                    c.Em = (Real)(E < 0.0 ? E / dv : 0.0);
+                    c.e = er;
+                    c.aeps = ar * epsr;
+                    c.aJ = (Real)((double)ar * J);
+                    const Real *C1p = C1 + (size_t)par * nx;
+                    c.c1 = valid ? C1p[i] : Real(0);
+                    c.c1n = valid ? C1p[wrapi(i + 1, nx)] : Real(0);
+                    c.c1p = valid ? C1p[wrapi(i - 1, nx)] : Real(0);
+                    const RowOut<Real> o =
+                        row_pass<Real, NV>(W + i, nx, valid, kv, c, lane, last, vtr,
+                                           HALO(par, 0, segn), HALO(par, 1, segp),
+                                           HALO(npar, 0, seg), HALO(npar, 1, seg));
+                    if (kv) {
+                        const Real c1n = c.aeps * (o.Sx * dvR);
+                        C1[(size_t)npar * nx + i] = c1n;
+                        Phi = -(double)o.phi * dv;
+                        const Real q = o.ww + Real(2) * c1n * o.wm + c1n * c1n * msq;
+                        Nn = epsr * (Real)sqrt((double)(q > Real(0) ? q * dvR : Real(0)));
+                    } else if (valid) {
+                        C1[(size_t)npar * nx + i] = Real(0);
                     }
-                    if (valid) {
-                        s_phi[i] = Phi;
-                        s_nrm[npar * nx + i] = Nn;
-                    }
+                } else if (valid) {
+                    C1[(size_t)npar * nx + i] = Real(0);
+                }
+                if (valid) {
+                    s_phi[i] = Phi;
+                    s_nrm[npar * nx + i] = Nn;
                 }
             }
         }
@@ -520,75 +499,54 @@ __global__ void __launch_bounds__(STREAM ? 1024 : 512) k_fine(const FineUnit *__
     }
 
     // ---------------------------------------------------------- epilogue
-    if (nsteps > 0) {
-        const double dtdx = C->dt / C->dx;
-#pragma unroll
-        for (int k = 0; k < IPTM; ++k) {
-            const int i = k * BS + tid;
-            if (k < ipt && i < nx) s_rho[i] = s_rho[i] + dtdx * (s_phi[i] - s_phi[wrapi(i - 1, nx)]);
-        }
-    }
-    if (hybrid) apply_status((int)(nsteps & 1));
+    if (nsteps > 0) density_update();
+    const int fpar = (int)(nsteps & 1);
+    if (hybrid) apply_status(fpar);
 #pragma unroll
     for (int k = 0; k < IPTM; ++k) {
         const int i = k * BS + tid;
         if (k < ipt && i < nx) {
             U.rho_out[i] = s_rho[i];
             if (U.mask_out) U.mask_out[i] = hybrid ? (int)((cmbits >> k) & 1u) : 1;
-            if constexpr (!STREAM) {
-                if (U.g_out) {
-#pragma unroll
-                    for (int j = 0; j < NV; ++j) gbuf[(size_t)j * nx + i] = gres[k][j];
-                }
-            }
+            const Real c1 = C1[(size_t)fpar * nx + i];
+            if (c1 != Real(0))
+                for (int j = 0; j < NV; ++j) W[(size_t)j * nx + i] += vtr[4 * j + 1] * c1;
+            C1[i] = Real(0);
+            C1[nx + i] = Real(0);
         }
     }
     if (U.kin) {
         const unsigned long long tot = wave_sum(kcount);
-        if ((tid & (kWave - 1)) == 0) atomicAdd(U.kin, tot);
+        if (lane == 0) atomicAdd(U.kin, tot);
     }
 #undef HALO
 }
 
-// Kernel classes: resident for small rows (state <= 128 VGPRs), streaming
-// otherwise.
+// Launch shape of a fine-sweep class: one workgroup per unit, up to 1024
+// threads, interfaces distributed over at most kMaxSlabs slabs.
 FineShape fine_shape(int prec, int nx, int nv, int force_stream, int force_block)
 {
+    (void)force_stream;
     FineShape s{};
     s.prec = prec;
     s.nv = nv;
+    s.stream = 1;
     const int realsz = prec == 0 ? 8 : 4;
-    int ipt = (nx + 511) / 512;
-    const int vgprs = ipt * nv * realsz / 4;
-    // Register-resident rows spill on gfx950 once the scheduler front-loads
-    // the cross-lane reads of a whole row; every class streams its rows
-    // through an L2-resident v-major buffer instead.
-    const bool resident = false && !force_stream && vgprs <= 128 && ipt <= 4;
-    if (resident) {
-        s.stream = 0;
-        s.ipt = ipt;
-        int b = (nx + ipt - 1) / ipt;
-        b = ((b + kWave - 1) / kWave) * kWave;
-        if (force_block > 0 && force_block * ipt >= nx && force_block <= 512) b = force_block;
-        s.block = b;
-    } else {
-        s.stream = 1;
-        int b = force_block > 0 ? force_block : 1024;
-        if (b > 1024) b = 1024;
-        int nxr = ((nx + kWave - 1) / kWave) * kWave;
-        if (b > nxr) b = nxr;
-        s.block = b;
-        s.ipt = (nx + b - 1) / b;
-    }
+    int nxr = ((nx + kWave - 1) / kWave) * kWave;
+    int b = force_block > 0 ? force_block : kFineBlock;
+    if (b > kFineBlock) b = kFineBlock;
+    if (b > nxr) b = nxr;
+    s.block = b;
+    s.ipt = (nx + b - 1) / b;
     const int nslot = s.ipt * (s.block / kWave);
     s.lds = fine_lds(nx, nv, realsz, nslot).total;
     return s;
 }
 
-template <typename Real, int NV, int IPT, bool STREAM>
+template <typename Real, int NV, int IPT>
 static hipError_t launch_one(const FineShape &s, const FineUnit *d, int n, hipStream_t st)
 {
-    auto kern = k_fine<Real, NV, IPT, STREAM>;
+    auto kern = k_fine<Real, NV, IPT>;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)s.lds);
     if (e != hipSuccess) return e;
@@ -599,13 +557,19 @@ static hipError_t launch_one(const FineShape &s, const FineUnit *d, int n, hipSt
 template <typename Real, int NV>
 static hipError_t launch_nv(const FineShape &s, const FineUnit *d, int n, hipStream_t st)
 {
-    if (s.stream) return launch_one<Real, NV, kMaxSlabs, true>(s, d, n, st);
-    return hipErrorInvalidValue;  // register-resident classes are not built
+    switch (s.ipt) {
+        case 1: return launch_one<Real, NV, 1>(s, d, n, st);
+        case 2: return launch_one<Real, NV, 2>(s, d, n, st);
+        case 3:
+        case 4: return launch_one<Real, NV, 4>(s, d, n, st);
+    }
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_fine(const FineShape &s, const FineUnit *d, int n, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
+    if (s.ipt > kMaxSlabs || s.block % kWave != 0) return hipErrorInvalidValue;
     if (s.prec == 0) {
         switch (s.nv) {
             case 16: return launch_nv<double, 16>(s, d, n, st);

@@ -35,11 +35,11 @@ def test_library_exports_every_declared_symbol():
 def test_footprint_of_the_configs():
     d2 = desc_of(wl.config2())
     b2 = sth.sth_footprint_bytes(d2)
-    # two (N+1)-slice perturbation buffers dominate: 2 * 65 * 512 * 64 * 8 bytes
-    assert 2 * 65 * 512 * 64 * 8 < b2 < 2 * 65 * 512 * 64 * 8 + (2 << 20)
+    # two (N+1)-slice state buffers (rows plus two projection rows) dominate
+    assert 2 * 65 * 512 * 66 * 8 < b2 < 2 * 65 * 512 * 66 * 8 + (2 << 20)
     d3 = desc_of(wl.config3(), precision=sth.FP32_BULK)
     b3 = sth.sth_footprint_bytes(d3)
-    assert 2 * 129 * 2048 * 128 * 4 < b3 < 2 * 129 * 2048 * 128 * 4 + (10 << 20)
+    assert 2 * 129 * 2048 * 130 * 4 < b3 < 2 * 129 * 2048 * 130 * 4 + (10 << 20)
 
 
 @pytest.mark.parametrize("field,value,code", [
@@ -55,6 +55,17 @@ def test_validation_errors(field, value, code):
         sth.sth_footprint_bytes(d)
     assert e.value.code == code
     assert sth.sth_last_error()
+
+
+def test_lds_limit_of_fp64_wide_velocity_grids():
+    d = desc_of(wl.small_hybrid(nx=2048, nv=128))
+    with pytest.raises(sth.StHError) as e:
+        sth.sth_footprint_bytes(d)
+    assert e.value.code == sth.STH_EINVAL
+    d.precision = sth.FP32_BULK
+    assert sth.sth_footprint_bytes(d) > 0
+    d = desc_of(wl.small_hybrid(nx=1024, nv=128))
+    assert sth.sth_footprint_bytes(d) > 0
 
 
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):

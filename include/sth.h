@@ -64,8 +64,7 @@ typedef struct sth_problem sth_problem;
 
 typedef struct {
     int           nx;          /* cells (= interfaces), 8 <= nx <= 2048        */
-    int           nv;          /* velocities, one of 16, 32, 64, 128 (FP64 with
-                                  nv = 128 needs nx <= 1024)                   */
+    int           nv;          /* velocities, one of 16, 32, 64, 128           */
     double        Lx;          /* torus length (> 0)                           */
     double        vstar;       /* velocity box half-width (> 0)                */
     const double *eps_iface;   /* [nx] Knudsen number at interfaces (> 0)      */

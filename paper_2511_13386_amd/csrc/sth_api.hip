@@ -92,7 +92,7 @@ int validate(const sth_problem_desc *d)
         return fail(STH_EINVAL, "unknown precision");
     if (d->flags & ~(STH_HYBRID | STH_FIELD | STH_LITERAL_R)) return fail(STH_EINVAL, "unknown flags");
     if (fine_shape(d->precision == STH_FP64 ? 0 : 1, d->nx, d->nv, 0, 0).lds > kMaxLds)
-        return fail(STH_EINVAL, "unit too large for one workgroup's LDS (FP64 with nv = 128 needs nx <= 1024)");
+        return fail(STH_EINVAL, "unit too large for one workgroup's LDS");
     return STH_OK;
 }
 
@@ -158,8 +158,13 @@ void velocity_table(int nv, double vstar, double dx, std::vector<double> &vtab, 
     const double dv = 2.0 * vstar / nv;
     std::vector<double> v(nv), M(nv);
     double Z = 0.0;
-    for (int j = 0; j < nv; ++j) {
+    // midpoint nodes, mirrored exactly (v_{nv-1-j} = -v_j) so that the fine
+    // sweep can share one table row between a velocity and its mirror
+    for (int j = 0; j < nv / 2; ++j) {
         v[j] = -vstar + (j + 0.5) * dv;
+        v[nv - 1 - j] = -v[j];
+    }
+    for (int j = 0; j < nv; ++j) {
         M[j] = std::exp(-0.5 * v[j] * v[j]);
         Z += M[j] * dv;
     }
@@ -212,26 +217,31 @@ double field_max(const std::vector<double> &rho, double rhobar, double dx)
     return mx;
 }
 
-// x-major double host array -> v-major Real device layout (host staging).
+// x-major double host array -> v-major Real device rows of stride ld
+// (host staging; padding zero).
 std::vector<char> to_vmajor(const double *g, int nx, int nv, int prec)
 {
-    std::vector<char> out((size_t)nx * nv * (prec == 0 ? 8 : 4));
+    const int ld = fine_ld(nx);
+    std::vector<char> out((size_t)ld * nv * (prec == 0 ? 8 : 4), 0);
     for (int p = 0; p < nx; ++p)
         for (int j = 0; j < nv; ++j) {
             const double x = g[(size_t)p * nv + j];
-            if (prec == 0) ((double *)out.data())[(size_t)j * nx + p] = x;
-            else ((float *)out.data())[(size_t)j * nx + p] = (float)x;
+            if (prec == 0) ((double *)out.data())[(size_t)j * ld + p] = x;
+            else ((float *)out.data())[(size_t)j * ld + p] = (float)x;
         }
     return out;
 }
 
 void from_vmajor(const std::vector<char> &in, int nx, int nv, int prec, double *g)
 {
+    const int ld = fine_ld(nx);
     for (int p = 0; p < nx; ++p)
         for (int j = 0; j < nv; ++j)
-            g[(size_t)p * nv + j] = prec == 0 ? ((const double *)in.data())[(size_t)j * nx + p]
-                                              : (double)((const float *)in.data())[(size_t)j * nx + p];
+            g[(size_t)p * nv + j] = prec == 0 ? ((const double *)in.data())[(size_t)j * ld + p]
+                                              : (double)((const float *)in.data())[(size_t)j * ld + p];
 }
+
+size_t vmajor_bytes(int nx, int nv, int realsz) { return (size_t)fine_ld(nx) * nv * realsz; }
 
 FineUnit make_unit(const sth_problem *p, int n)
 {
@@ -339,10 +349,12 @@ int sth_create(const sth_problem_desc *d, void *arena, size_t arena_bytes, sth_p
     c.vrow32 = p->at<float>(p->L.vrow32);
     std::vector<double> vrow64(4 * (size_t)nv);
     std::vector<float> vrow32(4 * (size_t)nv);
+    // row table of the fine sweep: |v_j|/dx, M_j, v_j M_j, M_{j+1} (M_nv = 0)
     for (int j = 0; j < nv; ++j)
         for (int q = 0; q < 4; ++q) {
-            vrow64[4 * j + q] = vtab[(size_t)q * nv + j];
-            vrow32[4 * j + q] = (float)vtab[(size_t)q * nv + j];
+            const double x = q < 3 ? vtab[(size_t)q * nv + j] : (j + 1 < nv ? vtab[(size_t)nv + j + 1] : 0.0);
+            vrow64[4 * j + q] = x;
+            vrow32[4 * j + q] = (float)x;
         }
 
     p->fc = c;
@@ -567,7 +579,7 @@ int sth_get_g(const sth_problem *p, int slice, double *host_out)
     if (!p || !host_out) return fail(STH_EINVAL, "null argument");
     if (slice < 1 || slice > p->N) return fail(STH_EINVAL, "slice must be in 1..N");
     HIPCHK(hipDeviceSynchronize());
-    std::vector<char> buf((size_t)p->nx * p->nv * p->realsz);
+    std::vector<char> buf(vmajor_bytes(p->nx, p->nv, p->realsz));
     HIPCHK(hipMemcpy(buf.data(), p->base + p->L.gend + (size_t)slice * p->gslab(), buf.size(),
                      hipMemcpyDeviceToHost));
     from_vmajor(buf, p->nx, p->nv, p->prec, host_out);
@@ -631,7 +643,7 @@ int sth_fine_run(sth_problem *p, const double *rho_in, const double *g_in, long 
     HIPCHK(hipStreamSynchronize(st));
     if (rho_out) HIPCHK(hipMemcpy(rho_out, d_rout, sizeof(double) * nx, hipMemcpyDeviceToHost));
     if (g_out) {
-        std::vector<char> buf((size_t)nx * p->nv * p->realsz);
+        std::vector<char> buf(vmajor_bytes(nx, p->nv, p->realsz));
         HIPCHK(hipMemcpy(buf.data(), d_gout, buf.size(), hipMemcpyDeviceToHost));
         from_vmajor(buf, nx, p->nv, p->prec, g_out);
     }

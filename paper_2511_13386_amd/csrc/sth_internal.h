@@ -25,16 +25,22 @@ struct FineConst {
     const double *e_p;    // [nx] exp(-dt/eps_p^2)
     const double *a_p;    // [nx] -expm1(-dt/eps_p^2)
     const double *vtab;   // [4][nv]: |v_j|/dx, M_j, v_j M_j, v_j
-    const double *vrow64; // [nv][4]: the same table row-wise, float64
-    const float *vrow32;  // [nv][4]: the same table row-wise, float32
+    const double *vrow64; // [nv][4]: |v_j|/dx, M_j, v_j M_j, M_{j+1} (M_nv = 0), float64
+    const float *vrow32;  // [nv][4]: the same row table, float32
 };
 
+// Row stride of the v-major perturbation arrays: nx padded to a multiple of
+// the wavefront, so that every row access of a wavefront is in bounds.
+__host__ __device__ inline int fine_ld(int nx) { return (nx + kWave - 1) / kWave * kWave; }
+
 // Per-unit state slot in global memory (elements of the working precision):
-// rows W[nv][nx] (v-major) and the lazy projection C1[2][nx].  After a sweep
-// W holds the perturbation.
+// rows W[nv][ld] (v-major, padding lanes zero), the lazy projection
+// C1[2][ld] and the halo rows H[2 parity][2 side][ld/64][nv/2] of the
+// wavefront segments.  After a sweep W holds the perturbation.
+__host__ __device__ inline size_t fine_halo_off(int nx, int nv) { return ((size_t)nv + 2) * (size_t)fine_ld(nx); }
 __host__ __device__ inline size_t fine_slot_elems(int nx, int nv)
 {
-    return (size_t)nv * nx + 2 * (size_t)nx;
+    return fine_halo_off(nx, nv) + 2 * (size_t)(fine_ld(nx) / kWave) * (size_t)nv;
 }
 
 // One fine-propagation unit: one slice of one problem.
@@ -42,8 +48,8 @@ struct FineUnit {
     FineConst c;              // problem constants by value (scalar loads)
     const double *rho_in;     // [nx] density at the slice start
     double *rho_out;          // [nx] density at the slice end
-    const void *g_in;         // [nv][nx] v-major start perturbation, Real; NULL = 0
-    void *g_out;              // [nv][nx] v-major end perturbation, Real; NULL = not stored
+    const void *g_in;         // [nv][ld] v-major start perturbation, Real; NULL = 0
+    void *g_out;              // [nv][ld] v-major end perturbation, Real (a full slot)
                               // (required by the streaming kernels: it is their state)
     unsigned long long *kin;  // kinetic interface-steps counter (atomic add)
     int *mask_out;            // [nx] final cell status, or NULL
@@ -55,7 +61,8 @@ struct FineShape {
     int prec;     // 0 = FP64, 1 = FP32 bulk
     int nv;
     int ipt;      // interfaces per thread (slabs)
-    int stream;   // 1 = perturbation streamed from global memory every step
+    int stream;   // 1 = rows streamed from the unit slot every step; 0 = resident
+                  // in registers for the whole slice
     int block;    // threads per workgroup
     size_t lds;   // dynamic LDS bytes
 };
@@ -67,7 +74,7 @@ hipError_t launch_fine(const FineShape &s, const FineUnit *d_units, int nunits, 
 struct LiftJob {
     const FineConst *pc;
     const double *rho;    // [nx]
-    void *g;              // [nv][nx] v-major Real
+    void *g;              // [nv][ld] v-major Real
     int lift_order;
 };
 hipError_t launch_lift(int prec, const LiftJob *d_jobs, int njobs, int nx, hipStream_t st);
@@ -92,7 +99,7 @@ hipError_t launch_coarse(const CoarseJob &job, int nx, hipStream_t st);
 struct DiagJob {
     const FineConst *pc;
     const double *rho;    // [nx]
-    const void *g;        // [nv][nx] v-major Real or NULL (0)
+    const void *g;        // [nv][ld] v-major Real or NULL (0)
     double *out;          // [5][nx]: E, J, Phi, N, R
     int *mask;            // [nx]
 };

@@ -10,16 +10,12 @@
 // problem for the whole slice (all its fine steps in one persistent launch).
 // Thread t owns interfaces/cells p = k*B + t (slab k), one lane per
 // interface, so every velocity moment of an interface is an in-register sum
-// and the x-upwind neighbour is one lane away (cross-lane shift; the two wave
-// edges read a double-buffered LDS halo).  The perturbation of the slice
-// stays in VGPRs for the whole slice when it fits ("resident"), otherwise it
-// is streamed from a v-major global buffer each step (coalesced: lanes are
-// consecutive interfaces).  Per fine step the workgroup needs three barriers:
-//   P1  density update from the previous fluxes, interface status, wave
-//       prefix sums of (rho - rhobar) dx                       | B1
-//   P2  field E (Gauss law, zero-mean gauge), flux J, cell-centred J  | B2
-//   P3  transport + projection + relaxation of kinetic interfaces, flux
-//       Phi, norms; remainder R and the cell rule                  | B3
+// and the x-upwind neighbour is one lane away (DPP shift of the wavefront;
+// the two wave edges read a double-buffered LDS halo).  The perturbation is
+// streamed each step from a v-major global buffer that stays resident in the
+// XCD's L2 (coalesced: lanes are consecutive interfaces), read and written
+// once per cell and step.  The macroscopic quantities (rho, E, J, Phi,
+// norms, status) live in LDS.  Three barriers per fine step (see k_fine).
 #include "sth_internal.h"
 #include "sth.h"
 
@@ -49,6 +45,51 @@ __device__ __forceinline__ T wave_sum(T x)
     return x;
 }
 
+// DPP move of a double (both halves with the same control); lanes without a
+// source or outside row_mask read 0.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_f64(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWMASK, 0xf, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWMASK, 0xf, false);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Inclusive prefix sum over the 64 lanes with DPP: row_shr 1, 2, 4, 8 inside
+// each row of 16 lanes, then row_bcast:15 and row_bcast:31 across rows.
+__device__ __forceinline__ double wave_scan_f64(double x)
+{
+    x += dpp_f64<0x111, 0xf>(x);
+    x += dpp_f64<0x112, 0xf>(x);
+    x += dpp_f64<0x114, 0xf>(x);
+    x += dpp_f64<0x118, 0xf>(x);
+    x += dpp_f64<0x142, 0xa>(x);
+    x += dpp_f64<0x143, 0xc>(x);
+    return x;
+}
+
+// Value of lane l (wavefront-uniform l) in every lane.
+__device__ __forceinline__ double lane_value(double x, int l)
+{
+    const long long b = __double_as_longlong(x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)b, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Sum over the 64 lanes, in every lane.
+__device__ __forceinline__ double wave_total_f64(double x) { return lane_value(wave_scan_f64(x), kWave - 1); }
+
+// Returns x unchanged but hides its value from the optimiser: values derived
+// from it inside a loop are recomputed there instead of being hoisted into
+// registers held across the loop.
+__device__ __forceinline__ int opaque_v(int x)
+{
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
 // Central 7-point stencils of Table 1 (derivative orders 1..3), offsets -3..3.
 __device__ __forceinline__ double fd1(const double *f, int i, int n)
 {
@@ -74,9 +115,11 @@ __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(
 
 // LDS layout of the fine kernel.  Same function on host (sizing) and device.
 struct FineLds {
-    size_t rho, jc, phi, E, nrm, cm, tot, wtot, jtot, halo, total;
+    size_t rho, jc, phi, E, nrm, cm, crit, tot, wtot, jtot, c1, halo, total;
 };
-__host__ __device__ inline FineLds fine_lds(int nx, int nv, int realsz, int nslot)
+// res: the resident kernel, which also keeps the lazy projection c1[2][nx]
+// and the halo rows [2 parity][2 side][nseg][nv/2] in LDS.
+__host__ __device__ inline FineLds fine_lds(int nx, int nv, int realsz, int nslot, bool res)
 {
     FineLds L;
     size_t o = 0;
@@ -84,12 +127,14 @@ __host__ __device__ inline FineLds fine_lds(int nx, int nv, int realsz, int nslo
     L.jc = o;   o = align16(o + sizeof(double) * nx);
     L.phi = o;  o = align16(o + sizeof(double) * nx);
     L.E = o;    o = align16(o + sizeof(double) * nx);
-    L.nrm = o;  o = align16(o + (size_t)realsz * 2 * nx);
-    L.cm = o;   o = align16(o + sizeof(unsigned char) * nx);
+    L.nrm = o;  o = align16(o + (size_t)realsz * nx);
+    L.cm = o;   o = align16(o + sizeof(unsigned char) * 2 * nx);
+    L.crit = o; o = align16(o + sizeof(unsigned char) * nx);
     L.tot = o;  o = align16(o + sizeof(double) * nslot);
     L.wtot = o; o = align16(o + sizeof(double) * nslot);
     L.jtot = o; o = align16(o + sizeof(double) * nslot);
-    L.halo = o; o = align16(o + (size_t)realsz * 2 * 2 * ((nx + kWave - 1) / kWave) * (nv / 2));
+    L.c1 = o;   if (res) o = align16(o + (size_t)realsz * 2 * nx);
+    L.halo = o; if (res) o = align16(o + (size_t)realsz * 2 * 2 * ((nx + kWave - 1) / kWave) * (nv / 2));
     L.total = o;
     return L;
 }
@@ -97,104 +142,336 @@ __host__ __device__ inline FineLds fine_lds(int nx, int nv, int realsz, int nslo
 
 // ------------------------------------------------------------ fine sweep
 // Row state.  A unit's perturbation lives in a v-major global buffer
-// W[j][p] (lanes = consecutive interfaces, so every row access is coalesced)
-// followed by C1[2][p].  The projection of the micro-macro step is applied
-// lazily: the stored row is w = g - M c1 with c1 = a eps <A> from the step that
-// produced it, and every read reconstructs g = w + M c1.  One step therefore
-// reads and writes each cell once:
+// W[j][p] with rows padded to a multiple of the wavefront (lanes =
+// consecutive interfaces, so every row access is one coalesced, unmasked
+// load or store), followed by C1[2][p] and the halo rows.  The projection of
+// the micro-macro step is applied lazily: the stored row is w = g - M c1 with
+// c1 = a eps <A> from the step that produced it, and every read reconstructs
+// g = w + M c1.  One step therefore reads and writes each cell once:
 //   g_j  = w_j + M_j c1
 //   A_j  = |v_j|/dx (g_j - g_up,j) + (G_{j+1/2} - G_{j-1/2})/dv
 //   w'_j = e g_j - a eps A_j - a J v_j M_j          (= g'_j - M_j a eps <A>)
 //   c1'  = a eps <A> = a eps dv sum_j |v_j|/dx (g_j - g_up,j)
-// (the velocity part of <A> telescopes to zero with zero-flux ends), and the
-// moments of g' follow from running sums of w':
-//   Phi = -dv sum v_j w'_j                         (sum_j v_j M_j = 0)
-//   |g'|^2 = dv (sum w'^2 + 2 c1' sum w' M + c1'^2 sum M^2).
-constexpr int kChunk = 8;  // velocities per software-pipelined chunk
+// (the velocity part of <A> telescopes to zero with zero-flux ends).  The
+// same pass yields the flux of g' and the norm of g:
+//   Phi = -dv sum v_j w'_j   (sum_j v_j M_j = 0),   |g|^2 = dv sum g_j^2.
+// Interfaces that are not kinetic run the same pass with e = a = 0, which
+// keeps their rows at zero without a branch.  The upwind neighbour in x is
+// one lane away; the wavefront's edge lanes read it from the halo rows
+// H[parity][side][segment][HV] (side 0: v<0 half of a segment's first
+// interface, side 1: v>0 half of its last), double-buffered by step parity
+// and kept in global memory, so that the velocity loop touches no LDS.
 constexpr int kFineBlock = 512;  // threads per fine-sweep workgroup at most
 
 // Uniform per-velocity constants are read through the constant address space
 // so that they are scalar loads into SGPRs, not vector registers.
 template <typename Real>
 using ConstPtr = const __attribute__((address_space(4))) Real *;
+// Global memory pointer (global, not flat, loads and stores).
+template <typename Real>
+using GlobPtr = __attribute__((address_space(1))) Real *;
+
+// Whole-wavefront shifts by one lane (DPP wave_shl:1 / wave_shr:1): lane l
+// gets x of lane l+1 (from_next_or) or l-1 (from_prev_or); the lane without
+// a source keeps old.
+__device__ __forceinline__ int dpp_next_or(int old, int x) { return __builtin_amdgcn_update_dpp(old, x, 0x130, 0xf, 0xf, false); }
+__device__ __forceinline__ int dpp_prev_or(int old, int x) { return __builtin_amdgcn_update_dpp(old, x, 0x138, 0xf, 0xf, false); }
+
+__device__ __forceinline__ float from_next_or(float old, float x)
+{
+    return __int_as_float(dpp_next_or(__float_as_int(old), __float_as_int(x)));
+}
+__device__ __forceinline__ float from_prev_or(float old, float x)
+{
+    return __int_as_float(dpp_prev_or(__float_as_int(old), __float_as_int(x)));
+}
+__device__ __forceinline__ double from_next_or(double old, double x)
+{
+    const long long b = __double_as_longlong(x), a = __double_as_longlong(old);
+    const unsigned lo = (unsigned)dpp_next_or((int)a, (int)b);
+    const unsigned hi = (unsigned)dpp_next_or((int)(a >> 32), (int)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ double from_prev_or(double old, double x)
+{
+    const long long b = __double_as_longlong(x), a = __double_as_longlong(old);
+    const unsigned lo = (unsigned)dpp_prev_or((int)a, (int)b);
+    const unsigned hi = (unsigned)dpp_prev_or((int)(a >> 32), (int)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Unit slot storage is addressed through a buffer resource: wavefront-
+// uniform base and row offset (scalar registers) plus a per-lane byte offset
+// that stays fixed over a row pass, so a row access costs no vector address
+// arithmetic.
+constexpr int kBufferFlags = 0x00020000;  // raw buffer, gfx9 family descriptor word 3
+
+template <typename Real>
+__device__ __forceinline__ Real buf_load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff);
+template <>
+__device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+__device__ __forceinline__ void buf_store(double x, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff)
+{
+    typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, voff, soff, 0);
+}
+__device__ __forceinline__ void buf_store(float x, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, voff, soff, 0);
+}
+
+// Returns p unchanged but hides its value from the optimiser, so that loads
+// through it stay inside the step loop instead of being hoisted (the hoisted
+// per-velocity constants would not fit in scalar registers).
+template <typename T>
+__device__ __forceinline__ T opaque(T p)
+{
+    asm volatile("" : "+s"(p));
+    return p;
+}
+
+// Pins a running sum in its register at this point of the program: the
+// compiler may otherwise sink a whole chain of accumulations to the point
+// where the sum is used, keeping every term alive until then.
+__device__ __forceinline__ void keep(double &x) { asm volatile("" : "+v"(x)); }
+__device__ __forceinline__ void keep(float &x) { asm volatile("" : "+v"(x)); }
 
 template <typename Real>
 struct RowCoef {
-    Real Ep, Em, e, aeps, aJ;  // E+/dv, E-/dv, exp(-dt/eps^2), a eps, a J
-    Real c1, c1n, c1p;         // lazy projection of this row and its neighbours
+    Real Ep, Em, e, aeps, aJ;  // E+/dv, E-/dv, exp(-dt/eps^2), a eps, a J (0 if not kinetic)
+    Real c1, c1n, c1p;         // lazy projection of this interface and of p+1, p-1
 };
 
 template <typename Real>
 struct RowOut {
-    Real Sx, phi, ww, wm;      // sum |v|/dx (g - g_up), sum v w', sum w'^2, sum w' M
+    Real Sx, phi, gg;          // sum |v|/dx (g - g_up), sum sign(v)|v|/dx w', sum g^2
 };
 
-// One kinetic-interface row.  lastlane: last valid lane of the segment; the
-// wave-edge upwind neighbours come from the halo rows hnext (v<0 half of row
-// p+1) and hprev (v>0 half of row p-1), stored raw (w form).
-template <typename Real, int NV>
-__device__ __forceinline__ RowOut<Real> row_pass(Real *__restrict__ Wp, int nx, bool valid, bool kin,
-                                                 const RowCoef<Real> &c, int lane, int lastlane,
-                                                 ConstPtr<Real> vt, const Real *hnext, const Real *hprev,
-                                                 Real *hfirst_out, Real *hlast_out)
+// Byte offsets of one row pass in the unit slot (wavefront-uniform except vo).
+struct RowIO {
+    __amdgpu_buffer_rsrc_t rs;  // the unit slot
+    unsigned vo;                // lane: byte offset of its interface in a row
+    unsigned rowb;              // bytes per row
+    unsigned hn, hp;            // halos read: v<0 half of interface p+1 (next segment's first),
+                                // v>0 half of interface p-1 (previous segment's last)
+    unsigned hno, hpo;          // halos written: this segment's first (v<0) and last (v>0) interface
+};
+
+// Software-pipelined chunk of velocity pairs (j, NV-1-j): rows and halo
+// values of CH pairs.  Chunk length per velocity grid: an even number of
+// chunks per half, and a rolled chunk loop wherever the grid has more than
+// two chunks (a straight run of chunks lets the compiler stretch live
+// ranges across them).
+template <int NV>
+constexpr int pair_chunk_len() { return NV == 32 ? 2 : 4; }
+template <typename Real, int CH>
+struct PairBuf {
+    Real wn[CH], wp[CH], hn[CH], hp[CH];
+};
+
+// One chunk of velocity pairs t0.. of a row.  A pair couples v_j < 0 (j = t,
+// upwind neighbour p+1) with its mirror v_m = -v_j (m = NV-1-t, upwind
+// neighbour p-1); both share |v|/dx, M and |v M|, so one row of the table
+// serves two velocities.  The v<0 half runs up from j = 0 carrying the
+// G flux of its lower face, the v>0 half runs down from m = NV-1 carrying
+// that of its upper face; they meet at the middle pair (LAST).  On entry
+// cur holds the stored rows and halos of this chunk and gj, gm the
+// reconstructed g of its first pair; the chunk loads the next chunk into nxt
+// (ping-pong, no register copies).  The wavefront's edge lanes keep the halo
+// value in the DPP shift (no source lane); in a ragged segment (RAGGED) the
+// last valid lane is not a wavefront edge and selects its halo explicitly.
+template <typename Real, int NV, bool LAST, bool RAGGED, int CH>
+__device__ __forceinline__ void pair_chunk(int t0, const RowIO &io, const RowCoef<Real> &c, bool first, bool last,
+                                           ConstPtr<Real> vt, const PairBuf<Real, CH> &cur, PairBuf<Real, CH> &nxt,
+                                           Real &gj, Real &gm, Real &Glo, Real &Ghi, RowOut<Real> &o)
 {
     constexpr int HV = NV / 2;
-    RowOut<Real> o{0, 0, 0, 0};
-    Real Glo = 0;
-    Real cur[kChunk + 1];
+    constexpr unsigned R = sizeof(Real);
+    // keep the scheduler from hoisting later chunks' loads into this one
+    __builtin_amdgcn_sched_barrier(0);
+    if (!LAST) {
 #pragma unroll
-    for (int t = 0; t <= kChunk; ++t)
-        cur[t] = (valid && t < NV) ? Wp[(size_t)t * nx] : Real(0);
+        for (int u = 0; u < CH; ++u) {
+            const int t = t0 + CH + u;
+            nxt.wn[u] = buf_load<Real>(io.rs, io.vo, (unsigned)t * io.rowb);
+            nxt.wp[u] = buf_load<Real>(io.rs, io.vo, (unsigned)(NV - 1 - t) * io.rowb);
+            nxt.hn[u] = buf_load<Real>(io.rs, 0u, io.hn + (unsigned)t * R);
+            nxt.hp[u] = buf_load<Real>(io.rs, 0u, io.hp + (unsigned)(HV - 1 - t) * R);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+        const int t = t0 + u, j = t, m = NV - 1 - t;
+        const Real cx = vt[4 * t], M = vt[4 * t + 1], vM = vt[4 * t + 2], Mn = vt[4 * t + 3];
+        Real gjn, gmn;  // g_{j+1}, g_{m-1}
+        if (u + 1 < CH) {
+            gjn = cur.wn[u + 1] + Mn * c.c1;
+            gmn = cur.wp[u + 1] + Mn * c.c1;
+        } else if (!LAST) {
+            gjn = nxt.wn[0] + Mn * c.c1;
+            gmn = nxt.wp[0] + Mn * c.c1;
+        } else {  // middle pair: rows HV-1 and HV are each other's neighbours
+            gjn = gm;
+            gmn = gj;
+        }
+        // upwind neighbours in x
+        const Real hj = cur.hn[u] + M * c.c1n;
+        Real gxj = from_next_or(hj, gj);
+        if (RAGGED) gxj = last ? hj : gxj;
+        const Real hm = cur.hp[u] + M * c.c1p;
+        const Real gxm = from_prev_or(hm, gm);
+        // G fluxes in v: G_{j+1/2} and G_{m-1/2} (the same face at the middle)
+        const Real Gj = c.Ep * gj + c.Em * gjn;
+        const Real Gm = (LAST && u == CH - 1) ? Gj : c.Ep * gmn + c.Em * gm;
+        const Real gvj = Gj - Glo, gvm = Ghi - Gm;
+        Glo = Gj;
+        Ghi = Gm;
+        const Real dgj = gj - gxj, dgm = gm - gxm;
+        o.Sx += cx * dgj;
+        o.Sx += cx * dgm;
+        const Real Aj = cx * dgj + gvj, Am = cx * dgm + gvm;
+        const Real wj = c.e * gj - c.aeps * Aj - c.aJ * vM;
+        const Real wm = c.e * gm - c.aeps * Am + c.aJ * vM;
+        buf_store(wj, io.rs, io.vo, (unsigned)j * io.rowb);
+        buf_store(wm, io.rs, io.vo, (unsigned)m * io.rowb);
+        if (first) buf_store(wj, io.rs, 0u, io.hno + (unsigned)j * R);
+        if (last) buf_store(wm, io.rs, 0u, io.hpo + (unsigned)(m - HV) * R);
+        o.phi += cx * (wm - wj);
+        o.gg += gj * gj;
+        o.gg += gm * gm;
+        keep(o.Sx);
+        keep(o.phi);
+        keep(o.gg);
+        gj = gjn;
+        gm = gmn;
+    }
+}
+
+// One row (interface) of a wavefront segment: every velocity pair, chunk by
+// chunk.  first/last: the lane is the first / last valid interface of its
+// segment (it writes the halos of its segment).
+template <typename Real, int NV, bool RAGGED>
+__device__ __forceinline__ RowOut<Real> row_pass(const RowIO &io, const RowCoef<Real> &c, bool first, bool last,
+                                                 ConstPtr<Real> vt)
+{
+    constexpr int HV = NV / 2, CH = pair_chunk_len<NV>();
+    constexpr unsigned R = sizeof(Real);
+    RowOut<Real> o{0, 0, 0};
+    PairBuf<Real, CH> A, B;
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+        A.wn[u] = buf_load<Real>(io.rs, io.vo, (unsigned)u * io.rowb);
+        A.wp[u] = buf_load<Real>(io.rs, io.vo, (unsigned)(NV - 1 - u) * io.rowb);
+        A.hn[u] = buf_load<Real>(io.rs, 0u, io.hn + (unsigned)u * R);
+        A.hp[u] = buf_load<Real>(io.rs, 0u, io.hp + (unsigned)(HV - 1 - u) * R);
+    }
+    Real Glo = 0, Ghi = 0;  // zero-flux velocity ends
+    Real gj = A.wn[0] + vt[1] * c.c1, gm = A.wp[0] + vt[1] * c.c1;
 #pragma unroll 1
-    for (int j0 = 0; j0 < NV; j0 += kChunk) {
-        Real nxt[kChunk];
+    for (int t0 = 0; t0 < HV - 2 * CH; t0 += 2 * CH) {
+        pair_chunk<Real, NV, false, RAGGED, CH>(t0, io, c, first, last, vt, A, B, gj, gm, Glo, Ghi, o);
+        pair_chunk<Real, NV, false, RAGGED, CH>(t0 + CH, io, c, first, last, vt, B, A, gj, gm, Glo, Ghi, o);
+    }
+    pair_chunk<Real, NV, false, RAGGED, CH>(HV - 2 * CH, io, c, first, last, vt, A, B, gj, gm, Glo, Ghi, o);
+    pair_chunk<Real, NV, true, RAGGED, CH>(HV - CH, io, c, first, last, vt, B, A, gj, gm, Glo, Ghi, o);
+    return o;
+}
+
+// Resident form of a row pass: the rows of the interface live in registers
+// (Wr[j], w form) for the whole slice, the halo rows in LDS (hn/hp read,
+// hno/hpo written, all indexed by pair).  Same arithmetic as pair_chunk.
+// The scalar table row and the two halo values of pair t+1 are requested
+// right after the first use of those of pair t, so that the single wait on
+// the LDS/scalar counter at the top of each pair finds them complete.  In a
+// ragged segment the lane after the last valid one holds a copy of the v<0
+// half of interface 0 (its periodic neighbour), so the DPP shift needs no
+// per-lane select.
+template <typename Real, int NV>
+__device__ __forceinline__ RowOut<Real> row_pass_res(Real (&Wr)[NV], const RowCoef<Real> &c, bool first, bool last,
+                                                     ConstPtr<Real> vt, const Real *hn, const Real *hp, Real *hno,
+                                                     Real *hpo)
+{
+    constexpr int HV = NV / 2;
+    RowOut<Real> o{0, 0, 0};
+    Real Glo = 0, Ghi = 0;  // zero-flux velocity ends
+    Real cx = vt[0], M = vt[1], vM = vt[2], Mn = vt[3];
+    Real hjv = hn[0], hmv = hp[HV - 1];
+    Real gj = Wr[0] + M * c.c1, gm = Wr[NV - 1] + M * c.c1;
 #pragma unroll
-        for (int t = 0; t < kChunk; ++t) {
-            const int jj = j0 + kChunk + 1 + t;
-            nxt[t] = (valid && jj < NV) ? Wp[(size_t)jj * nx] : Real(0);
+    for (int t = 0; t < HV; ++t) {
+        const int j = t, m = NV - 1 - t;
+        Real gjn, gmn;  // g_{j+1}, g_{m-1}
+        if (t + 1 < HV) {
+            gjn = Wr[j + 1] + Mn * c.c1;
+            gmn = Wr[m - 1] + Mn * c.c1;
+        } else {  // middle pair
+            gjn = gm;
+            gmn = gj;
         }
-        Real gnext = cur[0] + vt[4 * j0 + 1] * c.c1;
-#pragma unroll
-        for (int t = 0; t < kChunk; ++t) {
-            const int j = j0 + t;
-            const Real cx = vt[4 * j], M = vt[4 * j + 1], vM = vt[4 * j + 2], v = vt[4 * j + 3];
-            const Real gj = gnext;
-            gnext = (j + 1 < NV) ? cur[t + 1] + vt[4 * (j + 1) + 1] * c.c1 : Real(0);
-            Real gx;
-            if (j < HV) {      // v_j < 0: upwind neighbour is p+1
-                const Real h = hnext[j] + M * c.c1n;
-                gx = __shfl_down(gj, 1, kWave);
-                gx = lane == lastlane ? h : gx;
-            } else {           // v_j > 0: upwind neighbour is p-1
-                const Real h = hprev[j - HV] + M * c.c1p;
-                gx = __shfl_up(gj, 1, kWave);
-                gx = lane == 0 ? h : gx;
-            }
-            const Real ghi = (j < NV - 1) ? c.Ep * gj + c.Em * gnext : Real(0);
-            const Real dg = gj - gx;
-            const Real gv = ghi - Glo;
-            Glo = ghi;
-            o.Sx += cx * dg;
-            const Real A = cx * dg + gv;
-            Real w = c.e * gj - c.aeps * A - c.aJ * vM;
-            w = kin ? w : Real(0);
-            if (valid && kin) Wp[(size_t)j * nx] = w;
-            if (lane == 0 && j < HV) hfirst_out[j] = w;
-            if (lane == lastlane && j >= HV) hlast_out[j - HV] = w;
-            o.phi += v * w;
-            o.ww += w * w;
-            o.wm += w * M;
+        const Real hj = hjv + M * c.c1n, hm = hmv + M * c.c1p;
+        const Real cxc = cx, vMc = vM;
+        __builtin_amdgcn_sched_barrier(0);
+        if (t + 1 < HV) {
+            cx = vt[4 * (t + 1)];
+            M = vt[4 * (t + 1) + 1];
+            vM = vt[4 * (t + 1) + 2];
+            Mn = vt[4 * (t + 1) + 3];
+            hjv = hn[t + 1];
+            hmv = hp[HV - 2 - t];
         }
-        cur[0] = cur[kChunk];
-#pragma unroll
-        for (int t = 0; t < kChunk; ++t) cur[t + 1] = nxt[t];
+        __builtin_amdgcn_sched_barrier(0);
+        const Real gxj = from_next_or(hj, gj);
+        const Real gxm = from_prev_or(hm, gm);
+        const Real Gj = c.Ep * gj + c.Em * gjn;
+        const Real Gm = (t + 1 == HV) ? Gj : c.Ep * gmn + c.Em * gm;
+        const Real gvj = Gj - Glo, gvm = Ghi - Gm;
+        Glo = Gj;
+        Ghi = Gm;
+        const Real dgj = gj - gxj, dgm = gm - gxm;
+        o.Sx += cxc * dgj;
+        o.Sx += cxc * dgm;
+        const Real Aj = cxc * dgj + gvj, Am = cxc * dgm + gvm;
+        const Real wj = c.e * gj - c.aeps * Aj - c.aJ * vMc;
+        const Real wm = c.e * gm - c.aeps * Am + c.aJ * vMc;
+        Wr[j] = wj;
+        Wr[m] = wm;
+        if (first) hno[t] = wj;
+        if (last) hpo[HV - 1 - t] = wm;
+        o.phi += cxc * (wm - wj);
+        o.gg += gj * gj;
+        o.gg += gm * gm;
+        keep(o.Sx);
+        keep(o.phi);
+        keep(o.gg);
+        gj = gjn;
+        gm = gmn;
     }
     return o;
 }
 
 // Fine sweep: one workgroup per unit (slice), all fine steps of the slice in
 // one launch.  Threads own interfaces/cells p = k*B + t (slab k).
-template <typename Real, int NV, int IPTM>
+//
+// Per step n the workgroup needs three barriers:
+//   P1  cell status of step n from the criteria of step n-1 (interfaces
+//       turning fluid drop their perturbation), density update with the
+//       fluxes of step n-1, wave prefix sums of (rho - rhobar) dx     | B1
+//   P2  field E (Gauss law, zero-mean gauge), cell-centred flux J      | B2
+//   P3  remainder criterion of every cell; phase-space pass of every
+//       segment with a kinetic interface: transport, projection,
+//       relaxation, flux Phi and the norm of g                         | B3
+// RES: resident form (rows in registers, halos and c1 in LDS), for units
+// whose rows fit in the registers of their lanes; otherwise the rows stream
+// from the unit slot every step.
+template <typename Real, int NV, int IPTM, bool RES>
 __global__ void __launch_bounds__(kFineBlock) k_fine(const FineUnit *__restrict__ units)
 {
     constexpr int HV = NV / 2;
@@ -203,7 +480,10 @@ __global__ void __launch_bounds__(kFineBlock) k_fine(const FineUnit *__restrict_
     const FineUnit &U = units[blockIdx.x];
     const FineConst *__restrict__ C = &U.c;
     const int nx = C->nx;
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+    const int ld = fine_ld(nx);
+    // tid and lane are re-laundered at every step (see opaque_v)
+    int tid = threadIdx.x, lane = tid & (kWave - 1);
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int BS = blockDim.x, NW = BS / kWave;
     const int ipt = (nx + BS - 1) / BS;
     const int nseg = (nx + kWave - 1) / kWave;
@@ -216,61 +496,103 @@ __global__ void __launch_bounds__(kFineBlock) k_fine(const FineUnit *__restrict_
     const double *__restrict__ g_eps = C->eps_p;
     const double *__restrict__ g_epsc = C->eps_c;
 
-    const FineLds L = fine_lds(nx, NV, (int)sizeof(Real), nslot);
+    const FineLds L = fine_lds(nx, NV, (int)sizeof(Real), nslot, RES);
     double *s_rho = (double *)(smem + L.rho);
     double *s_jc = (double *)(smem + L.jc);
     double *s_phi = (double *)(smem + L.phi);
-    Real *s_nrm = (Real *)(smem + L.nrm);      // [2][nx]
-    unsigned char *s_cm = (unsigned char *)(smem + L.cm);
+    double *s_E = (double *)(smem + L.E);
+    Real *s_nrm = (Real *)(smem + L.nrm);      // [nx] eps ||g|| of the last pass
+    unsigned char *s_cm = (unsigned char *)(smem + L.cm);      // [2][nx] cell status by step parity
+    unsigned char *s_crit = (unsigned char *)(smem + L.crit);  // [nx] remainder criterion
     double *s_tot = (double *)(smem + L.tot);
     double *s_wtot = (double *)(smem + L.wtot);
     double *s_jtot = (double *)(smem + L.jtot);
-    double *s_E = (double *)(smem + L.E);
 
-    Real *W = (Real *)U.g_out;                 // [NV][nx] rows
-    Real *C1 = W + (size_t)NV * nx;            // [2][nx] lazy projection
-    Real *s_halo = (Real *)(smem + L.halo);    // [2 parity][2 side][nseg][HV] halo rows
-    // side 0: first row of a segment, v<0 half; side 1: last row, v>0 half
-#define HALO(par, side, seg) (s_halo + ((size_t)((par) * 2 + (side)) * nseg + (seg)) * HV)
+    GlobPtr<Real> W = (GlobPtr<Real>)U.g_out;        // [NV][ld] rows
+    GlobPtr<Real> C1 = W + (size_t)NV * ld;          // [2][ld] lazy projection
+    const size_t hoff = fine_halo_off(nx, NV);       // H[2 parity][2 side][nseg][HV]
+    GlobPtr<Real> H = W + hoff;
+    const __amdgpu_buffer_rsrc_t slot =
+        __builtin_amdgcn_make_buffer_rsrc(U.g_out, 0, (int)(sizeof(Real) * fine_slot_elems(nx, NV)), kBufferFlags);
+    // element offset of a halo row: side 0 = v<0 half of a segment's first
+    // interface, side 1 = v>0 half of its last
+#define HALO(par, side, seg) ((size_t)(((par) * 2 + (side)) * nseg + (seg)) * HV)
+    // resident form: rows in registers, c1 and halos in LDS
+    Real Wr[RES ? IPTM : 1][RES ? NV : 1];
+    Real *s_c1 = (Real *)(smem + L.c1);              // [2][nx]
+    Real *s_halo = (Real *)(smem + L.halo);          // [2][2][nseg][HV]
 
-    Real msq = 0;  // sum_j M_j^2
-    for (int j = 0; j < NV; ++j) {
-        const Real M = (Real)C->vtab[NV + j];
-        msq += M * M;
-    }
     // [NV][4] table in the working precision for the row passes
     const ConstPtr<Real> vtr = (ConstPtr<Real>)(sizeof(Real) == 8 ? (const void *)C->vrow64
                                                                  : (const void *)C->vrow32);
 
     const Real *gin = (const Real *)U.g_in;
     const Real dvR = (Real)C->dv;
+    const double rhobar = C->rhobar, dx = C->dx, dv = C->dv, m2 = C->m2;
+    const double inv_dx = 1.0 / dx, dtdx = C->dt / dx;
 
     unsigned kinbits = 0, cmbits = 0;          // status of the thread's slabs
     unsigned long long kcount = 0;
     double comp[IPTM];                         // compensation of the density sums
 
     // ---------------------------------------------------------- prologue
+    // Rows from g_in (padding lanes hold zero), halos of both parities,
+    // norms of g_in, status "kinetic" before the first rule.
 #pragma unroll
     for (int k = 0; k < IPTM; ++k) {
         const int i = k * BS + tid;
-        const bool valid = (k < ipt) && (i < nx);
         comp[k] = 0.0;
-        if (valid) s_rho[i] = U.rho_in[i];
         kinbits |= 1u << k;
         cmbits |= 1u << k;
-        if (valid) {
-            Real q = 0;
+        if constexpr (RES) {
+#pragma unroll
+            for (int j = 0; j < NV; ++j) Wr[k][j] = Real(0);
+        }
+        if (k < ipt && i < nseg * kWave) {
+            const bool valid = i < nx;
             const int seg = i / kWave, last = min(kWave - 1, nx - 1 - seg * kWave);
-            for (int j = 0; j < NV; ++j) {
-                const Real v = gin ? gin[(size_t)j * nx + i] : Real(0);
-                W[(size_t)j * nx + i] = v;
-                q += v * v;
-                if (lane == 0 && j < HV) HALO(0, 0, seg)[j] = v;
-                if (lane == last && j >= HV) HALO(0, 1, seg)[j - HV] = v;
+            Real q = 0;
+            if constexpr (RES) {
+#pragma unroll
+                for (int j = 0; j < NV; ++j) {
+                    const Real v = (gin && valid) ? gin[(size_t)j * ld + i] : Real(0);
+                    Wr[k][j] = v;
+                    q += v * v;
+                    if (lane == 0 && j < HV) {
+                        s_halo[HALO(0, 0, seg) + j] = v;
+                        s_halo[HALO(1, 0, seg) + j] = Real(0);
+                    }
+                    if (lane == last && j >= HV) {
+                        s_halo[HALO(0, 1, seg) + j - HV] = v;
+                        s_halo[HALO(1, 1, seg) + j - HV] = Real(0);
+                    }
+                }
+                if (valid) {
+                    s_c1[i] = Real(0);
+                    s_c1[nx + i] = Real(0);
+                }
+            } else {
+                for (int j = 0; j < NV; ++j) {
+                    const Real v = (gin && valid) ? gin[(size_t)j * ld + i] : Real(0);
+                    W[(size_t)j * ld + i] = v;
+                    q += v * v;
+                    if (lane == 0 && j < HV) {
+                        H[HALO(0, 0, seg) + j] = v;
+                        H[HALO(1, 0, seg) + j] = Real(0);
+                    }
+                    if (lane == last && j >= HV) {
+                        H[HALO(0, 1, seg) + j - HV] = v;
+                        H[HALO(1, 1, seg) + j - HV] = Real(0);
+                    }
+                }
+                C1[i] = Real(0);
+                C1[ld + i] = Real(0);
             }
-            C1[i] = Real(0);
-            C1[nx + i] = Real(0);
-            s_nrm[i] = (Real)g_eps[i] * (Real)sqrt((double)(q * dvR));
+            if (valid) {
+                s_rho[i] = U.rho_in[i];
+                s_nrm[i] = (Real)g_eps[i] * (Real)sqrt((double)(q * dvR));
+                s_cm[nx + i] = 1;
+            }
         }
     }
     __syncthreads();
@@ -280,16 +602,15 @@ __global__ void __launch_bounds__(kFineBlock) k_fine(const FineUnit *__restrict_
     // Wave prefix sums of d_i = (rho_i - rhobar) dx and of d_i (nx - i), whose
     // total is sum_p s_p (for the zero-mean gauge).
     auto macro_scan = [&]() {
-        const double rhobar = C->rhobar, dx = C->dx;
 #pragma unroll
         for (int k = 0; k < IPTM; ++k) {
             if (k < ipt) {
                 const int i = k * BS + tid;
                 const bool valid = i < nx;
                 const double d = valid ? (s_rho[i] - rhobar) * dx : 0.0;
-                incl[k] = wave_incl_scan(d, lane);
-                const double tot = __shfl(incl[k], kWave - 1, kWave);
-                const double w = wave_sum(valid ? d * (double)(nx - i) : 0.0);
+                incl[k] = wave_scan_f64(d);
+                const double tot = lane_value(incl[k], kWave - 1);
+                const double w = wave_total_f64(valid ? d * (double)(nx - i) : 0.0);
                 if (lane == 0) {
                     s_tot[k * NW + wid] = tot;
                     s_wtot[k * NW + wid] = w;
@@ -297,20 +618,19 @@ __global__ void __launch_bounds__(kFineBlock) k_fine(const FineUnit *__restrict_
             }
         }
     };
-    // Field E_p (Gauss law, zero-mean gauge), flux J_p, and (hybrid) the
-    // cell-centred J_i = d1 rho_i - E_i rho_i with E_i = E_p - d_p/2.
+    // Field E_p (Gauss law, zero-mean gauge), and (hybrid) the cell-centred
+    // J_i = d1 rho_i - E_i rho_i with E_i = E_p - d_p/2.
     auto macro_field = [&]() {
-        const double rhobar = C->rhobar, dx = C->dx, inv_dx = 1.0 / dx;
         const double t = lane < nslot ? s_tot[lane] : 0.0;
-        const double ex = wave_incl_scan(t, lane) - t;
-        const double Wsum = wave_sum(lane < nslot ? s_wtot[lane] : 0.0);
+        const double ex = wave_scan_f64(t) - t;
+        const double Wsum = wave_total_f64(lane < nslot ? s_wtot[lane] : 0.0);
         const double mean_s = Wsum / (double)nx;
 #pragma unroll
         for (int k = 0; k < IPTM; ++k) {
             if (k < ipt) {
                 const int i = k * BS + tid;
                 const bool valid = i < nx;
-                const double pre = __shfl(ex, k * NW + wid, kWave);
+                const double pre = lane_value(ex, k * NW + wid);
                 const double E = field ? (pre + incl[k]) - mean_s : 0.0;
                 double jsum = 0.0;
                 if (valid) {
@@ -324,19 +644,18 @@ __global__ void __launch_bounds__(kFineBlock) k_fine(const FineUnit *__restrict_
                     }
                 }
                 if (hybrid) {
-                    jsum = wave_sum(jsum);
+                    jsum = wave_total_f64(jsum);
                     if (lane == 0) s_jtot[k * NW + wid] = jsum;
                 }
             }
         }
     };
-    // Remainder R_i (eq. RemainderBis, Table 1 stencils) and the cell rule;
-    // initial = true applies the kinetic-cell rule to every cell.
-    auto macro_rule = [&](int par, bool initial) {
-        const double rhobar = C->rhobar, dx = C->dx, inv_dx = 1.0 / dx;
+    // Remainder R_i (eq. RemainderBis, Table 1 stencils) of the current
+    // density and its criterion bit.
+    auto macro_crit = [&]() {
         const double inv_dx2 = inv_dx * inv_dx, inv_dx3 = inv_dx2 * inv_dx;
-        const double eta0 = C->eta0, delta0 = C->delta0;
-        const double mJ = wave_sum(lane < nslot ? s_jtot[lane] : 0.0) / (double)nx;
+        const double eta0 = C->eta0;
+        const double mJ = wave_total_f64(lane < nslot ? s_jtot[lane] : 0.0) / (double)nx;
 #pragma unroll
         for (int k = 0; k < IPTM; ++k) {
             const int i = k * BS + tid;
@@ -357,36 +676,66 @@ __global__ void __launch_bounds__(kFineBlock) k_fine(const FineUnit *__restrict_
                 }
                 const double ec = g_epsc[i];
                 const double crit = literal ? fabs(R) : ec * ec * fabs(R);
-                const double nl = (double)s_nrm[par * nx + wrapi(i - 1, nx)];
-                const double nr = (double)s_nrm[par * nx + i];
-                const double nmax = nl > nr ? nl : nr;
-                int c;
-                if (initial || ((cmbits >> k) & 1u)) c = (nmax > delta0) || (crit > eta0);
-                else c = crit > eta0;
-                cmbits = (cmbits & ~(1u << k)) | ((unsigned)c << k);
-                s_cm[i] = (unsigned char)c;
+                s_crit[i] = (unsigned char)(crit > eta0);
             }
         }
     };
-    // Interface status of step n from s_cm; interfaces turning fluid get
-    // g' = 0 (row, lazy projection, norm, both halo parities).
-    auto apply_status = [&](int par) {
+    // Cell status of step n (parity par) from the criterion bits, the norms
+    // and the status of step n-1: a kinetic cell stays kinetic while a norm
+    // of its interfaces or its criterion exceeds the threshold, a fluid cell
+    // turns kinetic on the criterion.  Each thread evaluates its cell i and
+    // cell i+1, which fixes the status of interface i; interfaces turning
+    // fluid get g' = 0 (row, lazy projection, halos of both parities).
+    auto status = [&](int par) {
+        const double delta0 = C->delta0;
+        const unsigned char *cm_old = s_cm + (par ^ 1) * nx;
 #pragma unroll
         for (int k = 0; k < IPTM; ++k) {
             const int i = k * BS + tid;
             if (k < ipt && i < nx) {
-                const int kn = s_cm[i] | s_cm[wrapi(i + 1, nx)];
+                const int ip = wrapi(i + 1, nx), im = wrapi(i - 1, nx);
+                const double Nm = (double)s_nrm[im], N0 = (double)s_nrm[i], Np = (double)s_nrm[ip];
+                const double n0 = Nm > N0 ? Nm : N0, n1 = N0 > Np ? N0 : Np;
+                const int ci = s_crit[i] || (cm_old[i] && n0 > delta0);
+                const int cn = s_crit[ip] || (cm_old[ip] && n1 > delta0);
+                s_cm[par * nx + i] = (unsigned char)ci;
+                cmbits = (cmbits & ~(1u << k)) | ((unsigned)ci << k);
+                const int kn = ci | cn;
                 if (((kinbits >> k) & 1u) && !kn) {
+                    // rare; rolled loops keep their addresses out of the step loop's registers
                     const int seg = i / kWave, last = min(kWave - 1, nx - 1 - seg * kWave);
-                    for (int j = 0; j < NV; ++j) W[(size_t)j * nx + i] = Real(0);
+                    if constexpr (RES) {
+#pragma unroll
+                        for (int j = 0; j < NV; ++j) Wr[k][j] = Real(0);
+                        s_c1[i] = Real(0);
+                        s_c1[nx + i] = Real(0);
+#pragma unroll 1
+                        for (int pp = 0; pp < 2; ++pp) {
+                            if (lane == 0) {
+#pragma unroll 1
+                                for (int j = 0; j < HV; ++j) s_halo[HALO(pp, 0, seg) + j] = Real(0);
+                            }
+                            if (lane == last) {
+#pragma unroll 1
+                                for (int j = 0; j < HV; ++j) s_halo[HALO(pp, 1, seg) + j] = Real(0);
+                            }
+                        }
+                    } else {
+#pragma unroll 1
+                    for (int j = 0; j < NV; ++j) W[(size_t)j * ld + i] = Real(0);
                     C1[i] = Real(0);
-                    C1[nx + i] = Real(0);
-                    s_nrm[par * nx + i] = Real(0);
+                    C1[ld + i] = Real(0);
+#pragma unroll 1
                     for (int pp = 0; pp < 2; ++pp) {
-                        if (lane == 0)
-                            for (int j = 0; j < HV; ++j) HALO(pp, 0, seg)[j] = Real(0);
-                        if (lane == last)
-                            for (int j = 0; j < HV; ++j) HALO(pp, 1, seg)[j] = Real(0);
+                        if (lane == 0) {
+#pragma unroll 1
+                            for (int j = 0; j < HV; ++j) H[HALO(pp, 0, seg) + j] = Real(0);
+                        }
+                        if (lane == last) {
+#pragma unroll 1
+                            for (int j = 0; j < HV; ++j) H[HALO(pp, 1, seg) + j] = Real(0);
+                        }
+                    }
                     }
                 }
                 kinbits = (kinbits & ~(1u << k)) | ((unsigned)kn << k);
@@ -396,7 +745,6 @@ __global__ void __launch_bounds__(kFineBlock) k_fine(const FineUnit *__restrict_
     // Conservative density update with the fluxes of the previous step,
     // compensated (Kahan) so that long slices keep the mass to round-off.
     auto density_update = [&]() {
-        const double dtdx = C->dt / C->dx;
 #pragma unroll
         for (int k = 0; k < IPTM; ++k) {
             const int i = k * BS + tid;
@@ -411,108 +759,142 @@ __global__ void __launch_bounds__(kFineBlock) k_fine(const FineUnit *__restrict_
     };
 
     if (hybrid) {
+        // criterion bits of the initial density (the norms are those of g_in)
         macro_scan();
         __syncthreads();
         macro_field();
         __syncthreads();
-        macro_rule(0, true);
-    } else {
-#pragma unroll
-        for (int k = 0; k < IPTM; ++k) {
-            const int i = k * BS + tid;
-            if (k < ipt && i < nx) s_cm[i] = 1;
-        }
+        macro_crit();
+        __syncthreads();
     }
-    __syncthreads();
 
     // ---------------------------------------------------------- step loop
     for (long long n = 0; n < nsteps; ++n) {
         const int par = (int)(n & 1), npar = par ^ 1;
-        // P1: density update with the previous fluxes, interface status.
+        tid = opaque_v(tid);
+        lane = tid & (kWave - 1);
+        // P1: status of step n, density at step n, prefix sums.
+        if (hybrid) status(par);
         if (n > 0) density_update();
-        if (hybrid) apply_status(par);
         macro_scan();
         __syncthreads();  // B1
-        // P2: field and fluxes.
+        // P2: field and cell-centred flux.
         macro_field();
         __syncthreads();  // B2
-        // P3: phase-space pass of kinetic interfaces, then the cell rule.
-        {
-            const double dv = C->dv, m2 = C->m2, inv_dx = 1.0 / C->dx;
+        // P3: criterion bits, then the phase-space pass.
+        if (hybrid) macro_crit();
+        // one slab k: coefficients, row pass of a segment with a kinetic
+        // interface, flux and norm
+        auto slab = [&](int k, auto &&pass) {
+            const int i = k * BS + tid;
+            const int seg = k * NW + wid;  // wavefront-uniform
+            if (seg >= nseg) return;
+            const bool valid = i < nx;
+            const bool kv = valid && ((kinbits >> k) & 1u);
+            kcount += kv ? 1ull : 0ull;
+            const int iv = valid ? i : nx - 1;
+            const double r = s_rho[iv], rn = s_rho[wrapi(iv + 1, nx)];
+            const double E = valid ? s_E[iv] : 0.0;
+            const double J = (rn - r) * inv_dx - E * 0.5 * (r + rn);
+            double Phi = m2 * J;
+            Real Nn = 0;
+            if (__ballot(kv)) {
+                const int last = min(kWave - 1, nx - 1 - seg * kWave);
+                const int segn = seg + 1 == nseg ? 0 : seg + 1;
+                const int segp = seg == 0 ? nseg - 1 : seg - 1;
+                const Real er = (Real)g_e[iv], ar = (Real)g_a[iv];
+                const Real epsr = (Real)g_eps[iv];
+                RowCoef<Real> c;
+                c.Ep = (Real)(E > 0.0 ? E / dv : 0.0);
+                c.Em = (Real)(E < 0.0 ? E / dv : 0.0);
+                c.e = kv ? er : Real(0);
+                c.aeps = kv ? ar * epsr : Real(0);
+                c.aJ = kv ? (Real)((double)ar * J) : Real(0);
+                const RowOut<Real> o = pass(k, i, iv, seg, segn, segp, last, c);
+                const Real c1n = c.aeps * (o.Sx * dvR);
+                if constexpr (RES) {
+                    if (valid) s_c1[npar * nx + i] = c1n;
+                } else {
+                    C1[(size_t)npar * ld + i] = c1n;
+                }
+                if (kv) Phi = -((double)o.phi * dx) * dv;
+                Nn = epsr * (Real)sqrt((double)(o.gg * dvR));
+            }
+            if (valid) {
+                s_phi[i] = Phi;
+                s_nrm[i] = Nn;
+            }
+        };
+        if constexpr (RES) {
+#pragma unroll
+            for (int k = 0; k < IPTM; ++k) {
+                if (k < ipt)
+                    slab(k, [&](int kk, int i, int iv, int seg, int segn, int segp, int last, RowCoef<Real> &c) {
+                        const Real *hn = s_halo + HALO(par, 0, segn), *hp = s_halo + HALO(par, 1, segp);
+                        Real *hno = s_halo + HALO(npar, 0, seg), *hpo = s_halo + HALO(npar, 1, seg);
+                        // ragged segment: the lane after the last valid one mirrors the
+                        // v<0 half of interface 0 (w form, with its c1)
+                        const bool ghost = last < kWave - 1 && lane == last + 1;
+                        if (ghost) {
+#pragma unroll
+                            for (int j = 0; j < HV; ++j) Wr[k][j] = hn[j];
+                        }
+                        c.c1 = s_c1[par * nx + (ghost ? 0 : iv)];
+                        c.c1n = s_c1[par * nx + wrapi(iv + 1, nx)];
+                        c.c1p = s_c1[par * nx + wrapi(iv - 1, nx)];
+                        const ConstPtr<Real> vt = opaque(vtr);
+                        return row_pass_res<Real, NV>(Wr[k], c, lane == 0, lane == last, vt, hn, hp, hno, hpo);
+                    });
+            }
+        } else {
 #pragma unroll 1
             for (int k = 0; k < ipt; ++k) {
-                const int i = k * BS + tid;
-                const bool valid = i < nx;
-                const bool kv = valid && ((kinbits >> k) & 1u);
-                kcount += kv ? 1ull : 0ull;
-                const int seg = k * NW + wid;
-                double E = 0.0, J = 0.0;
-                if (valid) {
-                    const double r = s_rho[i], rn = s_rho[wrapi(i + 1, nx)];
-                    E = s_E[i];
-                    J = (rn - r) * inv_dx - E * 0.5 * (r + rn);
-                }
-                const unsigned long long any = __ballot(kv);
-                double Phi = m2 * J;
-                Real Nn = 0;
-                if (any && seg < nseg) {
-                    const int last = min(kWave - 1, nx - 1 - seg * kWave);
-                    const int segn = seg + 1 == nseg ? 0 : seg + 1;
-                    const int segp = seg == 0 ? nseg - 1 : seg - 1;
-                    const Real er = valid ? (Real)g_e[i] : Real(0);
-                    const Real ar = valid ? (Real)g_a[i] : Real(0);
-                    const Real epsr = valid ? (Real)g_eps[i] : Real(1);
-                    RowCoef<Real> c;
-                    c.Ep = (Real)(E > 0.0 ? E / dv : 0.0);
-                    c.Em = (Real)(E < 0.0 ? E / dv : 0.0);
-                    c.e = er;
-                    c.aeps = ar * epsr;
-                    c.aJ = (Real)((double)ar * J);
-                    const Real *C1p = C1 + (size_t)par * nx;
-                    c.c1 = valid ? C1p[i] : Real(0);
-                    c.c1n = valid ? C1p[wrapi(i + 1, nx)] : Real(0);
-                    c.c1p = valid ? C1p[wrapi(i - 1, nx)] : Real(0);
-                    const RowOut<Real> o =
-                        row_pass<Real, NV>(W + i, nx, valid, kv, c, lane, last, vtr,
-                                           HALO(par, 0, segn), HALO(par, 1, segp),
-                                           HALO(npar, 0, seg), HALO(npar, 1, seg));
-                    if (kv) {
-                        const Real c1n = c.aeps * (o.Sx * dvR);
-                        C1[(size_t)npar * nx + i] = c1n;
-                        Phi = -(double)o.phi * dv;
-                        const Real q = o.ww + Real(2) * c1n * o.wm + c1n * c1n * msq;
-                        Nn = epsr * (Real)sqrt((double)(q > Real(0) ? q * dvR : Real(0)));
-                    } else if (valid) {
-                        C1[(size_t)npar * nx + i] = Real(0);
-                    }
-                } else if (valid) {
-                    C1[(size_t)npar * nx + i] = Real(0);
-                }
-                if (valid) {
-                    s_phi[i] = Phi;
-                    s_nrm[npar * nx + i] = Nn;
-                }
+                slab(k, [&](int kk, int i, int iv, int seg, int segn, int segp, int last, RowCoef<Real> &c) {
+                    const GlobPtr<Real> C1p = C1 + (size_t)par * ld;
+                    c.c1 = C1p[i];
+                    c.c1n = C1p[wrapi(i + 1, nx)];
+                    c.c1p = C1p[wrapi(i - 1, nx)];
+                    constexpr unsigned R = sizeof(Real);
+                    RowIO io;
+                    io.rs = slot;
+                    io.vo = (unsigned)i * R;
+                    io.rowb = (unsigned)ld * R;
+                    io.hn = (unsigned)(hoff + HALO(par, 0, segn)) * R;
+                    io.hp = (unsigned)(hoff + HALO(par, 1, segp)) * R;
+                    io.hno = (unsigned)(hoff + HALO(npar, 0, seg)) * R;
+                    io.hpo = (unsigned)(hoff + HALO(npar, 1, seg)) * R;
+                    const ConstPtr<Real> vt = opaque(vtr);
+                    return last == kWave - 1 ? row_pass<Real, NV, false>(io, c, lane == 0, lane == last, vt)
+                                             : row_pass<Real, NV, true>(io, c, lane == 0, lane == last, vt);
+                });
             }
         }
-        if (hybrid) macro_rule(par, false);
         __syncthreads();  // B3
     }
 
     // ---------------------------------------------------------- epilogue
-    if (nsteps > 0) density_update();
     const int fpar = (int)(nsteps & 1);
-    if (hybrid) apply_status(fpar);
+    if (hybrid) status(fpar);
+    if (nsteps > 0) density_update();
 #pragma unroll
     for (int k = 0; k < IPTM; ++k) {
         const int i = k * BS + tid;
         if (k < ipt && i < nx) {
             U.rho_out[i] = s_rho[i];
             if (U.mask_out) U.mask_out[i] = hybrid ? (int)((cmbits >> k) & 1u) : 1;
-            const Real c1 = C1[(size_t)fpar * nx + i];
-            if (c1 != Real(0))
-                for (int j = 0; j < NV; ++j) W[(size_t)j * nx + i] += vtr[4 * j + 1] * c1;
-            C1[i] = Real(0);
-            C1[nx + i] = Real(0);
+            if constexpr (RES) {
+                const Real c1 = s_c1[fpar * nx + i];
+#pragma unroll
+                for (int j = 0; j < NV; ++j) W[(size_t)j * ld + i] = Wr[k][j] + vtr[4 * j + 1] * c1;
+            } else {
+                const Real c1 = C1[(size_t)fpar * ld + i];
+                if (c1 != Real(0)) {
+#pragma unroll 1
+                    for (int j = 0; j < NV; ++j) W[(size_t)j * ld + i] += vtr[4 * j + 1] * c1;
+                }
+                C1[i] = Real(0);
+                C1[ld + i] = Real(0);
+            }
         }
     }
     if (U.kin) {
@@ -524,13 +906,20 @@ __global__ void __launch_bounds__(kFineBlock) k_fine(const FineUnit *__restrict_
 
 // Launch shape of a fine-sweep class: one workgroup per unit, up to 1024
 // threads, interfaces distributed over at most kMaxSlabs slabs.
+// Rows of one lane fit its registers in the resident form (at most 128
+// VGPRs of the 256 that two wavefronts per SIMD leave to each).
+__host__ __device__ constexpr bool fine_resident_fits(int realsz, int iptm, int nv)
+{
+    return iptm * nv * (realsz / 4) <= 128;
+}
+
+static int fine_iptm(int ipt) { return ipt <= 2 ? ipt : 4; }
+
 FineShape fine_shape(int prec, int nx, int nv, int force_stream, int force_block)
 {
-    (void)force_stream;
     FineShape s{};
     s.prec = prec;
     s.nv = nv;
-    s.stream = 1;
     const int realsz = prec == 0 ? 8 : 4;
     int nxr = ((nx + kWave - 1) / kWave) * kWave;
     int b = force_block > 0 ? force_block : kFineBlock;
@@ -539,14 +928,17 @@ FineShape fine_shape(int prec, int nx, int nv, int force_stream, int force_block
     s.block = b;
     s.ipt = (nx + b - 1) / b;
     const int nslot = s.ipt * (s.block / kWave);
-    s.lds = fine_lds(nx, nv, realsz, nslot).total;
+    const bool res = !force_stream && s.ipt <= kMaxSlabs && fine_resident_fits(realsz, fine_iptm(s.ipt), nv) &&
+                     fine_lds(nx, nv, realsz, nslot, true).total <= kMaxLds;
+    s.stream = res ? 0 : 1;
+    s.lds = fine_lds(nx, nv, realsz, nslot, res).total;
     return s;
 }
 
-template <typename Real, int NV, int IPT>
+template <typename Real, int NV, int IPT, bool RES>
 static hipError_t launch_one(const FineShape &s, const FineUnit *d, int n, hipStream_t st)
 {
-    auto kern = k_fine<Real, NV, IPT>;
+    auto kern = k_fine<Real, NV, IPT, RES>;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)s.lds);
     if (e != hipSuccess) return e;
@@ -554,14 +946,25 @@ static hipError_t launch_one(const FineShape &s, const FineUnit *d, int n, hipSt
     return hipGetLastError();
 }
 
+template <typename Real, int NV, int IPT>
+static hipError_t launch_form(const FineShape &s, const FineUnit *d, int n, hipStream_t st)
+{
+    if constexpr (fine_resident_fits((int)sizeof(Real), IPT, NV)) {
+        if (!s.stream) return launch_one<Real, NV, IPT, true>(s, d, n, st);
+    } else {
+        if (!s.stream) return hipErrorInvalidValue;
+    }
+    return launch_one<Real, NV, IPT, false>(s, d, n, st);
+}
+
 template <typename Real, int NV>
 static hipError_t launch_nv(const FineShape &s, const FineUnit *d, int n, hipStream_t st)
 {
     switch (s.ipt) {
-        case 1: return launch_one<Real, NV, 1>(s, d, n, st);
-        case 2: return launch_one<Real, NV, 2>(s, d, n, st);
+        case 1: return launch_form<Real, NV, 1>(s, d, n, st);
+        case 2: return launch_form<Real, NV, 2>(s, d, n, st);
         case 3:
-        case 4: return launch_one<Real, NV, 4>(s, d, n, st);
+        case 4: return launch_form<Real, NV, 4>(s, d, n, st);
     }
     return hipErrorInvalidValue;
 }
@@ -687,6 +1090,7 @@ __global__ void __launch_bounds__(1024) k_lift(const LiftJob *__restrict__ jobs)
     __syncthreads();
     const double m2 = C->m2;
     const double *vt = C->vtab;
+    const int ld = fine_ld(nx);
     Real *g = (Real *)J.g;
     for (int p = threadIdx.x; p < nx; p += blockDim.x) {
         const double Jp = s_J[p], Kp = s_K[p], Ep = s_E[p];
@@ -701,7 +1105,7 @@ __global__ void __launch_bounds__(1024) k_lift(const LiftJob *__restrict__ jobs)
             double val = -v * M * Jp;
             if (J.lift_order >= 2) val += eps * (w * M * Kp);
             if (J.lift_order >= 3) val += eps * eps * (v * M * (dtJ - w * d1K - (2.0 + m2 - v * v) * Ep * Kp));
-            g[(size_t)j * nx + p] = (Real)val;
+            g[(size_t)j * ld + p] = (Real)val;
         }
     }
 }
@@ -847,6 +1251,7 @@ __global__ void __launch_bounds__(1024) k_diag(DiagJob J)
     double *oE = J.out, *oJ = J.out + nx, *oPhi = J.out + 2 * nx, *oN = J.out + 3 * nx, *oR = J.out + 4 * nx;
     const Real *g = (const Real *)J.g;
     const double *vt = C->vtab;
+    const int ld = fine_ld(nx);
     for (int p = threadIdx.x; p < nx; p += blockDim.x) s_rho[p] = J.rho[p];
     __syncthreads();
     block_poisson(s_rho, s_E, nx, dx, rhobar, field);
@@ -858,7 +1263,7 @@ __global__ void __launch_bounds__(1024) k_diag(DiagJob J)
         double ph = 0.0, q = 0.0;
         if (g) {
             for (int j = 0; j < nv; ++j) {
-                const double gv = (double)g[(size_t)j * nx + p];
+                const double gv = (double)g[(size_t)j * ld + p];
                 ph += vt[3 * nv + j] * gv * dv;
                 q += gv * gv * dv;
             }

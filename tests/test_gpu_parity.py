@@ -66,6 +66,26 @@ def test_multi_slab_streaming_fp64(orc):
     assert rel_err(gg, go) < G64
 
 
+@pytest.mark.parametrize("nx,nv,precision,steps,hybrid", [
+    (96, 128, sth.FP64, 600, True),        # rows streamed each step (too many for registers)
+    (1100, 16, sth.FP64, 300, True),       # resident rows, several slabs per thread
+    (600, 128, sth.FP32_BULK, 300, False),  # streamed, ragged second slab
+    (300, 64, sth.FP32_BULK, 600, False),   # resident, ragged
+])
+def test_both_row_forms(orc, nx, nv, precision, steps, hybrid):
+    """The resident (rows in registers) and streamed forms of the fine
+    kernel, each with ragged segments, against the oracle."""
+    inst = wl.small_hybrid(nx=nx, nv=nv)
+    inst.hybrid = hybrid
+    (rg, gg, mg, kg), (ro, go, mo, st) = _fine_pair(orc, inst, steps, precision=precision)
+    tol_r, tol_g = (RHO64, G64) if precision == sth.FP64 else (RHO32, G32)
+    assert rel_err(rg, ro) < tol_r
+    assert rel_err(gg, go) < tol_g
+    if precision == sth.FP64:
+        assert np.array_equal(mg, mo)
+        assert kg == st["kinetic_iface_steps"]
+
+
 @pytest.mark.parametrize("nv", [32, 128])
 def test_fp32_bulk_small(orc, nv):
     inst = wl.small_hybrid(nx=96, nv=nv)

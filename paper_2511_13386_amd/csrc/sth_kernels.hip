@@ -81,6 +81,32 @@ __device__ __forceinline__ double lane_value(double x, int l)
 // Sum over the 64 lanes, in every lane.
 __device__ __forceinline__ double wave_total_f64(double x) { return lane_value(wave_scan_f64(x), kWave - 1); }
 
+// Two inclusive prefix sums at once (independent chains interleave and fill
+// each other's DPP wait states); the row shifts zero-fill (bound_ctrl).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64_z(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, true);
+    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, true);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ void wave_scan2_f64(double &a, double &b)
+{
+    a += dpp_f64_z<0x111>(a);
+    b += dpp_f64_z<0x111>(b);
+    a += dpp_f64_z<0x112>(a);
+    b += dpp_f64_z<0x112>(b);
+    a += dpp_f64_z<0x114>(a);
+    b += dpp_f64_z<0x114>(b);
+    a += dpp_f64_z<0x118>(a);
+    b += dpp_f64_z<0x118>(b);
+    a += dpp_f64<0x142, 0xa>(a);
+    b += dpp_f64<0x142, 0xa>(b);
+    a += dpp_f64<0x143, 0xc>(a);
+    b += dpp_f64<0x143, 0xc>(b);
+}
+
 // Returns x unchanged but hides its value from the optimiser: values derived
 // from it inside a loop are recomputed there instead of being hoisted into
 // registers held across the loop.
@@ -111,6 +137,24 @@ __device__ __forceinline__ double fd3(const double *f, int i, int n)
            + (1.0) * f[wrapi(i + 2, n)] + (-1.0 / 8.0) * f[wrapi(i + 3, n)];
 }
 
+// The same stencils on an array with periodic ghost cells: f points at the
+// centre, f[-3..3] are valid.
+__device__ __forceinline__ double fd1g(const double *f)
+{
+    return (-1.0 / 60.0) * f[-3] + (3.0 / 20.0) * f[-2] + (-3.0 / 4.0) * f[-1] + (3.0 / 4.0) * f[1]
+           + (-3.0 / 20.0) * f[2] + (1.0 / 60.0) * f[3];
+}
+__device__ __forceinline__ double fd2g(const double *f)
+{
+    return (1.0 / 90.0) * f[-3] + (-3.0 / 20.0) * f[-2] + (3.0 / 2.0) * f[-1] + (-49.0 / 18.0) * f[0]
+           + (3.0 / 2.0) * f[1] + (-3.0 / 20.0) * f[2] + (1.0 / 90.0) * f[3];
+}
+__device__ __forceinline__ double fd3g(const double *f)
+{
+    return (1.0 / 8.0) * f[-3] + (-1.0) * f[-2] + (13.0 / 8.0) * f[-1] + (-13.0 / 8.0) * f[1] + (1.0) * f[2]
+           + (-1.0 / 8.0) * f[3];
+}
+
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
 
 // LDS layout of the fine kernel.  Same function on host (sizing) and device.
@@ -123,13 +167,15 @@ __host__ __device__ inline FineLds fine_lds(int nx, int nv, int realsz, int nslo
 {
     FineLds L;
     size_t o = 0;
-    L.rho = o;  o = align16(o + sizeof(double) * nx);
-    L.jc = o;   o = align16(o + sizeof(double) * nx);
-    L.phi = o;  o = align16(o + sizeof(double) * nx);
+    // periodic ghost cells: rho, jc [-3, nx+3); phi [-1, nx); nrm [-1, nx];
+    // cm (per parity) and crit [0, nx]
+    L.rho = o;  o = align16(o + sizeof(double) * (nx + 6));
+    L.jc = o;   o = align16(o + sizeof(double) * (nx + 6));
+    L.phi = o;  o = align16(o + sizeof(double) * (nx + 1));
     L.E = o;    o = align16(o + sizeof(double) * nx);
-    L.nrm = o;  o = align16(o + (size_t)realsz * nx);
-    L.cm = o;   o = align16(o + sizeof(unsigned char) * 2 * nx);
-    L.crit = o; o = align16(o + sizeof(unsigned char) * nx);
+    L.nrm = o;  o = align16(o + (size_t)realsz * (nx + 2));
+    L.cm = o;   o = align16(o + sizeof(unsigned char) * 2 * (nx + 1));
+    L.crit = o; o = align16(o + sizeof(unsigned char) * (nx + 1));
     L.tot = o;  o = align16(o + sizeof(double) * nslot);
     L.wtot = o; o = align16(o + sizeof(double) * nslot);
     L.jtot = o; o = align16(o + sizeof(double) * nslot);
@@ -151,7 +197,7 @@ __host__ __device__ inline FineLds fine_lds(int nx, int nv, int realsz, int nslo
 //   g_j  = w_j + M_j c1
 //   A_j  = |v_j|/dx (g_j - g_up,j) + (G_{j+1/2} - G_{j-1/2})/dv
 //   w'_j = e g_j - a eps A_j - a J v_j M_j          (= g'_j - M_j a eps <A>)
-//   c1'  = a eps <A> = a eps dv sum_j |v_j|/dx (g_j - g_up,j)
+//   c1'  = a eps <A> = a eps dv sum_j A_j
 // (the velocity part of <A> telescopes to zero with zero-flux ends).  The
 // same pass yields the flux of g' and the norm of g:
 //   Phi = -dv sum v_j w'_j   (sum_j v_j M_j = 0),   |g|^2 = dv sum g_j^2.
@@ -252,7 +298,7 @@ struct RowCoef {
 
 template <typename Real>
 struct RowOut {
-    Real Sx, phi, gg;          // sum |v|/dx (g - g_up), sum sign(v)|v|/dx w', sum g^2
+    Real Sx, phi, gg;          // sum A, sum sign(v)|v|/dx w', sum g^2
 };
 
 // Byte offsets of one row pass in the unit slot (wavefront-uniform except vo).
@@ -335,9 +381,9 @@ __device__ __forceinline__ void pair_chunk(int t0, const RowIO &io, const RowCoe
         Glo = Gj;
         Ghi = Gm;
         const Real dgj = gj - gxj, dgm = gm - gxm;
-        o.Sx += cx * dgj;
-        o.Sx += cx * dgm;
         const Real Aj = cx * dgj + gvj, Am = cx * dgm + gvm;
+        o.Sx += Aj;
+        o.Sx += Am;
         const Real wj = c.e * gj - c.aeps * Aj - c.aJ * vM;
         const Real wm = c.e * gm - c.aeps * Am + c.aJ * vM;
         buf_store(wj, io.rs, io.vo, (unsigned)j * io.rowb);
@@ -436,9 +482,9 @@ __device__ __forceinline__ RowOut<Real> row_pass_res(Real (&Wr)[NV], const RowCo
         Glo = Gj;
         Ghi = Gm;
         const Real dgj = gj - gxj, dgm = gm - gxm;
-        o.Sx += cxc * dgj;
-        o.Sx += cxc * dgm;
         const Real Aj = cxc * dgj + gvj, Am = cxc * dgm + gvm;
+        o.Sx += Aj;
+        o.Sx += Am;
         const Real wj = c.e * gj - c.aeps * Aj - c.aJ * vMc;
         const Real wm = c.e * gm - c.aeps * Am + c.aJ * vMc;
         Wr[j] = wj;
@@ -497,13 +543,31 @@ __global__ void __launch_bounds__(kFineBlock) k_fine(const FineUnit *__restrict_
     const double *__restrict__ g_epsc = C->eps_c;
 
     const FineLds L = fine_lds(nx, NV, (int)sizeof(Real), nslot, RES);
-    double *s_rho = (double *)(smem + L.rho);
-    double *s_jc = (double *)(smem + L.jc);
-    double *s_phi = (double *)(smem + L.phi);
+    // macroscopic arrays with periodic ghost cells (see fine_lds); the owner
+    // of a cell also writes its ghost copies
+    double *s_rho = (double *)(smem + L.rho) + 3;
+    double *s_jc = (double *)(smem + L.jc) + 3;
+    double *s_phi = (double *)(smem + L.phi) + 1;
     double *s_E = (double *)(smem + L.E);
-    Real *s_nrm = (Real *)(smem + L.nrm);      // [nx] eps ||g|| of the last pass
-    unsigned char *s_cm = (unsigned char *)(smem + L.cm);      // [2][nx] cell status by step parity
-    unsigned char *s_crit = (unsigned char *)(smem + L.crit);  // [nx] remainder criterion
+    Real *s_nrm = (Real *)(smem + L.nrm) + 1;  // eps ||g|| of the last pass
+    unsigned char *s_cm = (unsigned char *)(smem + L.cm);      // [2][nx+1] cell status by step parity
+    unsigned char *s_crit = (unsigned char *)(smem + L.crit);  // [nx+1] remainder criterion
+    const int ncm = nx + 1;
+    auto put_rho = [&](int i, double v) {
+        s_rho[i] = v;
+        if (i < 3) s_rho[nx + i] = v;
+        if (i >= nx - 3) s_rho[i - nx] = v;
+    };
+    auto put_jc = [&](int i, double v) {
+        s_jc[i] = v;
+        if (i < 3) s_jc[nx + i] = v;
+        if (i >= nx - 3) s_jc[i - nx] = v;
+    };
+    auto put_nrm = [&](int i, Real v) {
+        s_nrm[i] = v;
+        if (i == 0) s_nrm[nx] = v;
+        if (i == nx - 1) s_nrm[-1] = v;
+    };
     double *s_tot = (double *)(smem + L.tot);
     double *s_wtot = (double *)(smem + L.wtot);
     double *s_jtot = (double *)(smem + L.jtot);
@@ -529,7 +593,7 @@ __global__ void __launch_bounds__(kFineBlock) k_fine(const FineUnit *__restrict_
     const Real *gin = (const Real *)U.g_in;
     const Real dvR = (Real)C->dv;
     const double rhobar = C->rhobar, dx = C->dx, dv = C->dv, m2 = C->m2;
-    const double inv_dx = 1.0 / dx, dtdx = C->dt / dx;
+    const double inv_dx = 1.0 / dx, dtdx = C->dt / dx, inv_nx = 1.0 / (double)nx;
 
     unsigned kinbits = 0, cmbits = 0;          // status of the thread's slabs
     unsigned long long kcount = 0;
@@ -589,9 +653,10 @@ __global__ void __launch_bounds__(kFineBlock) k_fine(const FineUnit *__restrict_
                 C1[ld + i] = Real(0);
             }
             if (valid) {
-                s_rho[i] = U.rho_in[i];
-                s_nrm[i] = (Real)g_eps[i] * (Real)sqrt((double)(q * dvR));
-                s_cm[nx + i] = 1;
+                put_rho(i, U.rho_in[i]);
+                put_nrm(i, (Real)g_eps[i] * (Real)sqrt((double)(q * dvR)));
+                s_cm[ncm + i] = 1;
+                if (i == 0) s_cm[ncm + nx] = 1;
             }
         }
     }
@@ -608,9 +673,11 @@ __global__ void __launch_bounds__(kFineBlock) k_fine(const FineUnit *__restrict_
                 const int i = k * BS + tid;
                 const bool valid = i < nx;
                 const double d = valid ? (s_rho[i] - rhobar) * dx : 0.0;
-                incl[k] = wave_scan_f64(d);
-                const double tot = lane_value(incl[k], kWave - 1);
-                const double w = wave_total_f64(valid ? d * (double)(nx - i) : 0.0);
+                double a = d, b = valid ? d * (double)(nx - i) : 0.0;
+                wave_scan2_f64(a, b);
+                incl[k] = a;
+                const double tot = lane_value(a, kWave - 1);
+                const double w = lane_value(b, kWave - 1);
                 if (lane == 0) {
                     s_tot[k * NW + wid] = tot;
                     s_wtot[k * NW + wid] = w;
@@ -622,9 +689,10 @@ __global__ void __launch_bounds__(kFineBlock) k_fine(const FineUnit *__restrict_
     // J_i = d1 rho_i - E_i rho_i with E_i = E_p - d_p/2.
     auto macro_field = [&]() {
         const double t = lane < nslot ? s_tot[lane] : 0.0;
-        const double ex = wave_scan_f64(t) - t;
-        const double Wsum = wave_total_f64(lane < nslot ? s_wtot[lane] : 0.0);
-        const double mean_s = Wsum / (double)nx;
+        double a = t, b = lane < nslot ? s_wtot[lane] : 0.0;
+        wave_scan2_f64(a, b);
+        const double ex = a - t;
+        const double mean_s = lane_value(b, kWave - 1) * inv_nx;
 #pragma unroll
         for (int k = 0; k < IPTM; ++k) {
             if (k < ipt) {
@@ -638,8 +706,8 @@ __global__ void __launch_bounds__(kFineBlock) k_fine(const FineUnit *__restrict_
                     s_E[i] = E;
                     if (hybrid) {
                         const double Ec = field ? E - 0.5 * (r - rhobar) * dx : 0.0;
-                        const double jc = fd1(s_rho, i, nx) * inv_dx - Ec * r;
-                        s_jc[i] = jc;
+                        const double jc = fd1g(s_rho + i) * inv_dx - Ec * r;
+                        put_jc(i, jc);
                         jsum = jc;
                     }
                 }
@@ -655,20 +723,20 @@ __global__ void __launch_bounds__(kFineBlock) k_fine(const FineUnit *__restrict_
     auto macro_crit = [&]() {
         const double inv_dx2 = inv_dx * inv_dx, inv_dx3 = inv_dx2 * inv_dx;
         const double eta0 = C->eta0;
-        const double mJ = wave_total_f64(lane < nslot ? s_jtot[lane] : 0.0) / (double)nx;
+        const double mJ = wave_total_f64(lane < nslot ? s_jtot[lane] : 0.0) * inv_nx;
 #pragma unroll
         for (int k = 0; k < IPTM; ++k) {
             const int i = k * BS + tid;
             if (k < ipt && i < nx) {
                 const double r = s_rho[i];
                 const double jc = s_jc[i];
-                const double d1J = fd1(s_jc, i, nx) * inv_dx;
-                const double d3J = fd3(s_jc, i, nx) * inv_dx3;
+                const double d1J = fd1g(s_jc + i) * inv_dx;
+                const double d3J = fd3g(s_jc + i) * inv_dx3;
                 double R;
                 if (field) {
                     const double Ec = s_E[i] - 0.5 * (r - rhobar) * dx;
-                    const double d1r = fd1(s_rho, i, nx) * inv_dx;
-                    const double d2J = fd2(s_jc, i, nx) * inv_dx2;
+                    const double d1r = fd1g(s_rho + i) * inv_dx;
+                    const double d2J = fd2g(s_jc + i) * inv_dx2;
                     R = -d3J + Ec * d2J + (2.0 * r - 3.0 * rhobar) * d1J + 2.0 * jc * d1r
                         - d1r * (jc - mJ);
                 } else {
@@ -677,6 +745,7 @@ __global__ void __launch_bounds__(kFineBlock) k_fine(const FineUnit *__restrict_
                 const double ec = g_epsc[i];
                 const double crit = literal ? fabs(R) : ec * ec * fabs(R);
                 s_crit[i] = (unsigned char)(crit > eta0);
+                if (i == 0) s_crit[nx] = (unsigned char)(crit > eta0);
             }
         }
     };
@@ -688,17 +757,17 @@ __global__ void __launch_bounds__(kFineBlock) k_fine(const FineUnit *__restrict_
     // fluid get g' = 0 (row, lazy projection, halos of both parities).
     auto status = [&](int par) {
         const double delta0 = C->delta0;
-        const unsigned char *cm_old = s_cm + (par ^ 1) * nx;
+        const unsigned char *cm_old = s_cm + (par ^ 1) * ncm;
 #pragma unroll
         for (int k = 0; k < IPTM; ++k) {
             const int i = k * BS + tid;
             if (k < ipt && i < nx) {
-                const int ip = wrapi(i + 1, nx), im = wrapi(i - 1, nx);
-                const double Nm = (double)s_nrm[im], N0 = (double)s_nrm[i], Np = (double)s_nrm[ip];
+                const double Nm = (double)s_nrm[i - 1], N0 = (double)s_nrm[i], Np = (double)s_nrm[i + 1];
                 const double n0 = Nm > N0 ? Nm : N0, n1 = N0 > Np ? N0 : Np;
                 const int ci = s_crit[i] || (cm_old[i] && n0 > delta0);
-                const int cn = s_crit[ip] || (cm_old[ip] && n1 > delta0);
-                s_cm[par * nx + i] = (unsigned char)ci;
+                const int cn = s_crit[i + 1] || (cm_old[i + 1] && n1 > delta0);
+                s_cm[par * ncm + i] = (unsigned char)ci;
+                if (i == 0) s_cm[par * ncm + nx] = (unsigned char)ci;
                 cmbits = (cmbits & ~(1u << k)) | ((unsigned)ci << k);
                 const int kn = ci | cn;
                 if (((kinbits >> k) & 1u) && !kn) {
@@ -750,10 +819,10 @@ __global__ void __launch_bounds__(kFineBlock) k_fine(const FineUnit *__restrict_
             const int i = k * BS + tid;
             if (k < ipt && i < nx) {
                 const double r = s_rho[i];
-                const double y = dtdx * (s_phi[i] - s_phi[wrapi(i - 1, nx)]) - comp[k];
+                const double y = dtdx * (s_phi[i] - s_phi[i - 1]) - comp[k];
                 const double t = r + y;
                 comp[k] = (t - r) - y;
-                s_rho[i] = t;
+                put_rho(i, t);
             }
         }
     };
@@ -793,7 +862,7 @@ __global__ void __launch_bounds__(kFineBlock) k_fine(const FineUnit *__restrict_
             const bool kv = valid && ((kinbits >> k) & 1u);
             kcount += kv ? 1ull : 0ull;
             const int iv = valid ? i : nx - 1;
-            const double r = s_rho[iv], rn = s_rho[wrapi(iv + 1, nx)];
+            const double r = s_rho[iv], rn = s_rho[iv + 1];
             const double E = valid ? s_E[iv] : 0.0;
             const double J = (rn - r) * inv_dx - E * 0.5 * (r + rn);
             double Phi = m2 * J;
@@ -822,7 +891,8 @@ __global__ void __launch_bounds__(kFineBlock) k_fine(const FineUnit *__restrict_
             }
             if (valid) {
                 s_phi[i] = Phi;
-                s_nrm[i] = Nn;
+                if (i == nx - 1) s_phi[-1] = Phi;
+                put_nrm(i, Nn);
             }
         };
         if constexpr (RES) {
@@ -830,8 +900,12 @@ __global__ void __launch_bounds__(kFineBlock) k_fine(const FineUnit *__restrict_
             for (int k = 0; k < IPTM; ++k) {
                 if (k < ipt)
                     slab(k, [&](int kk, int i, int iv, int seg, int segn, int segp, int last, RowCoef<Real> &c) {
-                        const Real *hn = s_halo + HALO(par, 0, segn), *hp = s_halo + HALO(par, 1, segp);
-                        Real *hno = s_halo + HALO(npar, 0, seg), *hpo = s_halo + HALO(npar, 1, seg);
+                        // halo row addresses as vector registers (LDS addresses must be),
+                        // so that each access is the base plus an immediate offset
+                        const Real *hn = s_halo + opaque_v((int)HALO(par, 0, segn));
+                        const Real *hp = s_halo + opaque_v((int)HALO(par, 1, segp));
+                        Real *hno = s_halo + opaque_v((int)HALO(npar, 0, seg));
+                        Real *hpo = s_halo + opaque_v((int)HALO(npar, 1, seg));
                         // ragged segment: the lane after the last valid one mirrors the
                         // v<0 half of interface 0 (w form, with its c1)
                         const bool ghost = last < kWave - 1 && lane == last + 1;

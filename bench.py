@@ -33,6 +33,42 @@ sys.path.insert(0, ROOT)
 METRIC = "fine-step phase-space cell-updates/s FP32 vs FP64; parareal wall-clock; p50/p99"
 HBM_PEAK_GBS = 8000.0
 MACRO_BYTES_PER_IFACE_STEP = 64  # rho, E, J, Phi, e, a, eps, status per interface per step
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+# floating-point operations of one kinetic cell-update of the micro-macro
+# step: transport 7 (upwind difference and scaling, two-sided G flux and its
+# difference), projection 3, relaxation with source 5, flux moment 2, norm 2
+FLOPS_PER_CELL_UPDATE = 19
+KERNEL_SOURCES = ("paper_2511_13386_amd/csrc/sth_kernels.hip", "paper_2511_13386_amd/csrc/sth_internal.h")
+
+
+def sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload_key):
+    """HBM bytes per fine-sweep launch from the committed counter summary of
+    this workload, if it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"k_fine_{workload_key}_hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_sources_sha256") != sources_sha256():
+        return None
+    try:
+        return float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def parse():
@@ -49,7 +85,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run a plain 1 GiB device copy (HBM counter calibration)")
+                    help="also run a plain 1 GiB elementwise copy kernel (HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -174,6 +210,11 @@ def main():
                  for kin, it in zip(kin_per_iter, iface_steps)]
     avg_ms = float(np.mean(sweep_ms))
     achieved_gbs = float(np.mean([b / (ms * 1e-3) for b, ms in zip(alg_bytes, sweep_ms)])) / 1e9
+    alg_tflops = float(np.mean([kin * inst.nv * FLOPS_PER_CELL_UPDATE / (ms * 1e-3)
+                                for kin, ms in zip(kin_per_iter, sweep_ms)])) / 1e12
+    vec_peak = FP64_VECTOR_PEAK_TFLOPS if prec == sth.FP64 else FP32_VECTOR_PEAK_TFLOPS
+    workload_key = f"{inst.nx}x{inst.nv}_{args.precision}"
+    traffic = measured_traffic(workload_key)
     m0 = float(np.sum(inst.rho_in))
     mass_drift = float(np.max(np.abs(U.sum(axis=1) - m0)) / m0)
 
@@ -197,6 +238,8 @@ def main():
             "nx": inst.nx, "nv": inst.nv, "n_slices": inst.N, "T": inst.T,
             "fine_steps_per_slice": info.steps_per_slice, "fine_dt": info.dt,
             "parareal_iterations_timed": K, "parallelism": "single GPU, one workgroup per slice",
+            "fine_form": "resident rows" if info.fine_resident else "streamed rows",
+            "fine_block": info.fine_block,
         },
         "roofline": {
             "bound": "hbm",
@@ -204,8 +247,14 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved_gbs / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic,
         },
+        "vector_alu": {
+            "achieved": alg_tflops, "peak": vec_peak, "unit": "TFLOP/s",
+            "frac": alg_tflops / vec_peak, "flops_per_cell_update": FLOPS_PER_CELL_UPDATE,
+            "cus_busy": min(inst.N, 256), "cus": 256,
+        },
+        "fine_step_us": avg_ms * 1e3 / info.steps_per_slice,
         "fine_sweep_ms_avg": avg_ms,
         "fine_sweep_ms": sweep_ms,
         "kinetic_fraction": kin_total / max(sum(iface_steps), 1),
@@ -214,13 +263,14 @@ def main():
         "mass_drift_rel": mass_drift,
     }
     if args.copy_calibration:
-        x = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        # one elementwise kernel that reads 1 GiB and writes 1 GiB, for
+        # scaling the HBM byte counters
+        x = torch.zeros(1 << 28, dtype=torch.float32, device="cuda")
         y = torch.empty_like(x)
         torch.cuda.synchronize()
-        for _ in range(3):
-            y.copy_(x)
+        torch.neg(x, out=y)
         torch.cuda.synchronize()
-        out["copy_calibration_bytes"] = 1 << 30
+        out["copy_calibration"] = {"kernel": "torch.neg float32", "read_bytes": 1 << 30, "write_bytes": 1 << 30}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst, args.cpu_seconds)
     print(json.dumps(out), flush=True)

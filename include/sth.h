@@ -97,6 +97,9 @@ typedef struct {
                                       far (times nv = kinetic cell-updates)    */
     double    last_err;        /* successive error of the last correction      */
     size_t    footprint_bytes; /* device bytes held by the problem             */
+    int       fine_resident;   /* 1: the fine sweep keeps the rows of a slice
+                                  in registers; 0: streamed every step       */
+    int       fine_block;      /* threads per fine-sweep workgroup            */
 } sth_info;
 
 /* Device bytes a problem with this description needs (serving admission).

@@ -601,6 +601,9 @@ int sth_get_info(const sth_problem *p, sth_info *out)
     out->kinetic_iface_steps = tot;
     out->last_err = p->last_err;
     out->footprint_bytes = p->bytes;
+    const FineShape sh = fine_shape(p->prec, p->nx, p->nv, 0, 0);
+    out->fine_resident = sh.stream ? 0 : 1;
+    out->fine_block = sh.block;
     return STH_OK;
 }
 

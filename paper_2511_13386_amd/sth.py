@@ -61,6 +61,7 @@ class Info(ctypes.Structure):
         ("steps_per_slice", ctypes.c_longlong), ("k_done", ctypes.c_int),
         ("n_slices", ctypes.c_int), ("kinetic_iface_steps", ctypes.c_double),
         ("last_err", ctypes.c_double), ("footprint_bytes", ctypes.c_size_t),
+        ("fine_resident", ctypes.c_int), ("fine_block", ctypes.c_int),
     ]
 
 

@@ -16,6 +16,11 @@
  * (interface p lies between cells p and p+1, i.e. p is "i+1/2").
  *
  * All arrays are caller-owned.  Phase-space arrays are x-major: g[p*nv + j].
+ *
+ * Parity unpinned (no value independent of this oracle exists): the hybrid
+ * mask dynamics over long runs, the L = 2 and L = 3 lifting beyond zero mass
+ * and its slow-manifold order, and full parareal results at large sizes.
+ * Everything else is pinned by tests/test_oracle_pins.py.
  */
 #ifndef STH_ORACLE_H
 #define STH_ORACLE_H

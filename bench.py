@@ -84,6 +84,20 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--workload", choices=["config2", "batch", "serve"], default="config2",
+                    help="config2: the hybrid parareal problem the metric is quoted on; "
+                         "batch: many independent instances in one batched sweep per iteration")
+    ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--batch-T", type=float, default=0.01)
+    ap.add_argument("--batch-slices", type=int, default=32)
+    ap.add_argument("--baseline-every", type=int, default=20,
+                    help="batch: every n-th instance also runs alone in FP64 (the baseline form)")
+    ap.add_argument("--requests", type=int, default=200, help="serve: number of requests")
+    ap.add_argument("--serve-T-scale", type=float, default=1e-2,
+                    help="serve: request horizons T ~ U[0.1, 1] times this factor")
+    ap.add_argument("--load", type=float, default=0.7,
+                    help="serve: arrival rate as a fraction of the measured saturated throughput")
+    ap.add_argument("--budget-gib", type=float, default=8.0, help="serve: device arena for admission")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB elementwise copy kernel (HBM counter calibration)")
     return ap.parse_args()
@@ -127,6 +141,178 @@ def cpu_baseline(inst, target_s):
     }
 
 
+def run_batch(args, torch, sth, wl):
+    """Config 4: independent instances of mixed size and eps, all slices of all
+    instances in one batched fine sweep per parareal iteration, against the
+    plain FP64 single-instance form on a subset."""
+    insts = wl.batch_config(count=args.batch_count, T=args.batch_T, N=args.batch_slices)
+    prec = sth.FP64 if args.precision == "fp64" else sth.FP32_BULK
+    K = max(1, min(args.steps, args.batch_slices))
+
+    def desc(inst, precision, steps_override=0):
+        return sth.Desc(nx=inst.nx, nv=inst.nv, eps_iface=inst.eps_iface, eps_cell=inst.eps_cell,
+                        rho0=inst.rho_in, T=inst.T, n_slices=inst.N, k_max=K, tol=0.0,
+                        eta0=inst.eta0, delta0=inst.delta0, lift_order=1, start_mode=sth.START_CARRY,
+                        cfl_theta=inst.theta, flags=sth.FIELD | sth.HYBRID, precision=precision,
+                        steps_override=steps_override)
+
+    stream = torch.cuda.Stream()
+    if args.warmup > 0:  # every kernel class once, short slices
+        ws = [sth.Problem(desc(i, prec, steps_override=20)) for i in insts]
+        for w in ws:
+            sth.sth_coarse_sweep(w, stream)
+        sth.sth_fine_sweep_batched(ws, stream)
+        torch.cuda.synchronize()
+        for w in ws:
+            w.close()
+        print("# warmup done", file=sys.stderr, flush=True)
+
+    def solve(problems, precision_label):
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+        for p in problems:
+            sth.sth_coarse_sweep(p, stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(K):
+            with torch.cuda.stream(stream):
+                ev[k][0].record(stream)
+            sth.sth_fine_sweep_batched(problems, stream)
+            with torch.cuda.stream(stream):
+                ev[k][1].record(stream)
+            for p in problems:
+                sth.sth_parareal_correct(p, want_err=False, stream=stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = [a.elapsed_time(b) for a, b in ev]
+        kin = sum(p.info().kinetic_iface_steps * p.nv for p in problems)
+        return kin, ms, wall
+
+    problems = [sth.Problem(desc(i, prec)) for i in insts]
+    footprint = sum(p.info().footprint_bytes for p in problems)
+    kin, ms, wall = solve(problems, args.precision)
+    rate = kin / (sum(ms) * 1e-3)
+    print(f"# batched {len(problems)} instances: {kin:.3e} kinetic cell-updates in {sum(ms):.0f} ms of sweeps",
+          file=sys.stderr, flush=True)
+    U_batch = {i: sth.sth_get_rho(problems[i]) for i in range(0, len(insts), args.baseline_every)}
+    mass = max(float(np.max(np.abs(sth.sth_get_rho(p).sum(axis=1) - inst.rho_in.sum())) / abs(inst.rho_in.sum()))
+               for p, inst in zip(problems, insts))
+    for p in problems:
+        p.close()
+
+    # baseline: the same solves one instance at a time in FP64, on a subset
+    kin1 = ms1 = 0.0
+    errs = []
+    for i in sorted(U_batch):
+        p1 = sth.Problem(desc(insts[i], sth.FP64))
+        k1, m1, _ = solve([p1], "fp64")
+        kin1 += k1
+        ms1 += sum(m1)
+        U1 = sth.sth_get_rho(p1)
+        errs.append(float(np.max(np.abs(U_batch[i] - U1)) / np.max(np.abs(U1))))
+        p1.close()
+    rate1 = kin1 / (ms1 * 1e-3)
+    out = {
+        "metric": "batched fine-sweep kinetic cell-updates/s (independent instances, mixed sizes)",
+        "value": rate, "unit": "cell-updates/s", "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": float(np.mean(ms)), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if prec == sth.FP64 else "f32-bulk/f64-macro",
+        "data": "synthetic",
+        "config": {"workload": (f"{len(insts)} instances seed 1000+i, Nx in {{128..2048}}, Nv in {{32,64,128}}, "
+                                f"log10 eps ~ U[-4,0], 1-3 cosine modes, N={args.batch_slices}, T={args.batch_T}, "
+                                f"{K} parareal iterations, carried slice starts"),
+                   "instances": len(insts), "device_bytes": footprint},
+        "single_instance_fp64": {"value": rate1, "unit": "cell-updates/s",
+                                 "instances": len(U_batch),
+                                 "sample": f"every {args.baseline_every}-th instance, alone, FP64"},
+        "speedup_vs_single_fp64": rate / rate1,
+        "max_rel_rho_diff_vs_single_fp64": max(errs) if errs else None,
+        "mass_drift_rel_max": mass,
+        "parareal_wall_s": wall,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_serve(args, torch, sth, wl):
+    """Config 5: a Poisson stream of solve requests (sizes and eps as config 4,
+    horizons scaled), served with continuous batching in FP32-bulk; p50/p99
+    latency and throughput against the plain FP64 one-at-a-time form."""
+    from paper_2511_13386_amd import serving
+    R, K = args.requests, 2
+    u = (wl.uniform_pm1(4242, R) + 1.0) * 0.5
+    insts = []
+    for r in range(R):
+        T = (0.1 + 0.9 * u[r]) * args.serve_T_scale
+        insts.append(wl.random_instance(5000 + r, N=32, T=T))
+
+    def desc(inst, precision):
+        return sth.Desc(nx=inst.nx, nv=inst.nv, eps_iface=inst.eps_iface, eps_cell=inst.eps_cell,
+                        rho0=inst.rho_in, T=inst.T, n_slices=inst.N, k_max=K, tol=0.0,
+                        eta0=inst.eta0, delta0=inst.delta0, lift_order=1, start_mode=sth.START_CARRY,
+                        cfl_theta=inst.theta, flags=sth.FIELD | sth.HYBRID, precision=precision)
+
+    budget = int(args.budget_gib * (1 << 30))
+    srv = serving.Server(budget)
+    # warmup: every kernel class once
+    warm = [serving.Request(r, desc(i, sth.FP32_BULK), 0.0, 1) for r, i in enumerate(insts[:48])]
+    for w in warm:
+        w.desc.steps_override = 20
+    srv.run(warm)
+    torch.cuda.synchronize()
+
+    # saturated throughput: everything arrives at once
+    reqs = [serving.Request(r, desc(i, sth.FP32_BULK), 0.0, K) for r, i in enumerate(insts)]
+    t0 = time.perf_counter()
+    sat = srv.run(reqs)
+    sat_wall = time.perf_counter() - t0
+    sat_rate = R / sat_wall
+    print(f"# saturated: {R} requests in {sat_wall:.2f} s", file=sys.stderr, flush=True)
+
+    # Poisson arrivals at a fraction of the saturated rate
+    lam = args.load * sat_rate
+    arr = wl.poisson_arrivals(R, lam, seed=99)
+    reqs = [serving.Request(r, desc(i, sth.FP32_BULK), float(arr[r]), K) for r, i in enumerate(insts)]
+    t0 = time.perf_counter()
+    res = srv.run(reqs)
+    wall = time.perf_counter() - t0
+    pct = serving.latency_percentiles(res)
+    cells = sum(r.cell_updates for r in res)
+
+    # baseline: the same requests one at a time in FP64, FIFO in arrival order
+    service, diffs = [], []
+    stream = torch.cuda.Stream()
+    for r, inst in enumerate(insts):
+        p = sth.Problem(desc(inst, sth.FP64))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        sth.parareal_solve(p, K=K, fixed_iterations=True, stream=stream)
+        torch.cuda.synchronize()
+        service.append(time.perf_counter() - t1)
+        U = sth.sth_get_rho(p)
+        diffs.append(float(np.max(np.abs(res[r].rho - U)) / np.max(np.abs(U))))
+        p.close()
+    fin, lat1 = 0.0, []
+    for a, sv in zip(arr, service):
+        fin = max(fin, a) + sv
+        lat1.append(fin - a)
+    out = {
+        "metric": "serving: p50/p99 latency and throughput of hybrid parareal solve requests",
+        "value": R / wall, "unit": "requests/s", "n_gpus": 1, "steps": K, "warmup": 1,
+        "ms_per_step": wall * 1e3 / max(srv.ticks, 1), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32-bulk/f64-macro", "data": "synthetic",
+        "config": {"workload": (f"{R} requests seed 5000+r, sizes/eps as config 4, T ~ U[0.1,1] x "
+                                f"{args.serve_T_scale}, N=32, {K} parareal iterations, Poisson arrivals at "
+                                f"{args.load} x saturated rate, arena {args.budget_gib} GiB"),
+                   "arrival_rate_per_s": lam},
+        "latency_s": pct, "cell_updates_per_s": cells / wall,
+        "saturated_requests_per_s": sat_rate,
+        "fp64_one_at_a_time": {"requests_per_s": R / sum(service),
+                               "latency_s": {"p50": float(np.percentile(lat1, 50)),
+                                             "p99": float(np.percentile(lat1, 99))}},
+        "max_rel_rho_diff_fp32_served_vs_fp64_alone": max(diffs),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -141,6 +327,12 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
+    if args.workload == "batch":
+        run_batch(args, torch, sth, wl)
+        return
+    if args.workload == "serve":
+        run_serve(args, torch, sth, wl)
+        return
     prec = sth.FP64 if args.precision == "fp64" else sth.FP32_BULK
     inst = wl.config2(seed=args.seed, nx=args.nx, nv=args.nv, N=args.slices, T=args.T,
                       K=args.steps)

@@ -126,6 +126,37 @@ int acquire_table(size_t bytes, int *slot_out)
     return STH_OK;
 }
 
+// Side streams of a device for batches with several kernel classes: the
+// classes run concurrently, forked from and joined back into the caller's
+// stream with events (default priority, non-blocking).
+constexpr int kSideStreams = 3;
+struct SidePool {
+    hipStream_t s[kSideStreams] = {};
+    hipEvent_t fork = nullptr, join[kSideStreams] = {};
+    bool ready = false;
+};
+std::mutex g_side_mu, g_side_issue_mu;
+std::vector<SidePool> g_side;
+
+int side_pool(SidePool **out)
+{
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_side_mu);
+    if ((int)g_side.size() <= dev) g_side.resize(dev + 1);
+    SidePool &P = g_side[dev];
+    if (!P.ready) {
+        for (int i = 0; i < kSideStreams; ++i) {
+            HIPCHK(hipStreamCreateWithFlags(&P.s[i], hipStreamNonBlocking));
+            HIPCHK(hipEventCreateWithFlags(&P.join[i], hipEventDisableTiming));
+        }
+        HIPCHK(hipEventCreateWithFlags(&P.fork, hipEventDisableTiming));
+        P.ready = true;
+    }
+    *out = &P;
+    return STH_OK;
+}
+
 }  // namespace
 
 struct sth_problem {
@@ -480,20 +511,54 @@ int sth_fine_sweep_batched(sth_problem *const *probs, int count, void *stream)
         std::vector<FineUnit> host(items.size());
         for (size_t t = 0; t < items.size(); ++t) host[t] = items[t].unit;
         HIPCHK(hipMemcpyAsync(dtab, host.data(), sizeof(FineUnit) * host.size(), hipMemcpyHostToDevice, st));
+        // kernel classes: runs of equal shape in the sorted table
+        struct Group {
+            FineShape sh;
+            size_t begin, end;
+            double cost;
+        };
+        std::vector<Group> groups;
         size_t begin = 0;
         while (begin < items.size()) {
             size_t end = begin + 1;
             FineShape sh = items[begin].shape;
             size_t lds = sh.lds;
+            double cost = items[begin].cost;
             while (end < items.size() && items[end].shape.prec == sh.prec && items[end].shape.nv == sh.nv &&
                    items[end].shape.stream == sh.stream && items[end].shape.ipt == sh.ipt &&
                    items[end].shape.block == sh.block) {
                 lds = std::max(lds, items[end].shape.lds);
+                cost += items[end].cost;
                 ++end;
             }
             sh.lds = lds;
-            HIPCHK(launch_fine(sh, dtab + begin, (int)(end - begin), st));
+            groups.push_back({sh, begin, end, cost});
             begin = end;
+        }
+        if (groups.size() == 1) {
+            HIPCHK(launch_fine(groups[0].sh, dtab, (int)items.size(), st));
+        } else {
+            // several classes: the costliest on the caller's stream, the others
+            // spread over the side streams, all concurrent
+            std::stable_sort(groups.begin(), groups.end(),
+                             [](const Group &a, const Group &b) { return a.cost > b.cost; });
+            SidePool *P = nullptr;
+            int rc2 = side_pool(&P);
+            if (rc2) return rc2;
+            // the fork/join events are shared: issue one batch at a time
+            std::lock_guard<std::mutex> lk(g_side_issue_mu);
+            const int nside = std::min<int>(kSideStreams, (int)groups.size() - 1);
+            HIPCHK(hipEventRecord(P->fork, st));
+            for (int i = 0; i < nside; ++i) HIPCHK(hipStreamWaitEvent(P->s[i], P->fork, 0));
+            for (size_t g = 0; g < groups.size(); ++g) {
+                const int lane = (int)(g % (size_t)(nside + 1));
+                hipStream_t gs = lane == 0 ? st : P->s[lane - 1];
+                HIPCHK(launch_fine(groups[g].sh, dtab + groups[g].begin, (int)(groups[g].end - groups[g].begin), gs));
+            }
+            for (int i = 0; i < nside; ++i) {
+                HIPCHK(hipEventRecord(P->join[i], P->s[i]));
+                HIPCHK(hipStreamWaitEvent(st, P->join[i], 0));
+            }
         }
         HIPCHK(hipEventRecord(g_pool[slot].ev, st));
         g_pool[slot].used = true;

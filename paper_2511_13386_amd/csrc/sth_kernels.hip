@@ -296,9 +296,13 @@ struct RowCoef {
     Real c1, c1n, c1p;         // lazy projection of this interface and of p+1, p-1
 };
 
+// Running sums of a row pass.  They are kept in FP64 in both precisions:
+// each velocity pair is summed in the working precision and the pair sums
+// accumulate in FP64 (in FP32-bulk this bounds the rounding of the flux,
+// the projection and the norm over long slices, at one conversion per sum).
 template <typename Real>
 struct RowOut {
-    Real Sx, phi, gg;          // sum A, sum sign(v)|v|/dx w', sum g^2
+    double Sx, phi, gg;        // sum A, sum sign(v)|v|/dx w', sum g^2
 };
 
 // Byte offsets of one row pass in the unit slot (wavefront-uniform except vo).
@@ -382,17 +386,15 @@ __device__ __forceinline__ void pair_chunk(int t0, const RowIO &io, const RowCoe
         Ghi = Gm;
         const Real dgj = gj - gxj, dgm = gm - gxm;
         const Real Aj = cx * dgj + gvj, Am = cx * dgm + gvm;
-        o.Sx += Aj;
-        o.Sx += Am;
+        o.Sx += (double)(Aj + Am);
         const Real wj = c.e * gj - c.aeps * Aj - c.aJ * vM;
         const Real wm = c.e * gm - c.aeps * Am + c.aJ * vM;
         buf_store(wj, io.rs, io.vo, (unsigned)j * io.rowb);
         buf_store(wm, io.rs, io.vo, (unsigned)m * io.rowb);
         if (first) buf_store(wj, io.rs, 0u, io.hno + (unsigned)j * R);
         if (last) buf_store(wm, io.rs, 0u, io.hpo + (unsigned)(m - HV) * R);
-        o.phi += cx * (wm - wj);
-        o.gg += gj * gj;
-        o.gg += gm * gm;
+        o.phi += (double)(cx * (wm - wj));
+        o.gg += (double)(gj * gj + gm * gm);
         keep(o.Sx);
         keep(o.phi);
         keep(o.gg);
@@ -483,17 +485,15 @@ __device__ __forceinline__ RowOut<Real> row_pass_res(Real (&Wr)[NV], const RowCo
         Ghi = Gm;
         const Real dgj = gj - gxj, dgm = gm - gxm;
         const Real Aj = cxc * dgj + gvj, Am = cxc * dgm + gvm;
-        o.Sx += Aj;
-        o.Sx += Am;
+        o.Sx += (double)(Aj + Am);
         const Real wj = c.e * gj - c.aeps * Aj - c.aJ * vMc;
         const Real wm = c.e * gm - c.aeps * Am + c.aJ * vMc;
         Wr[j] = wj;
         Wr[m] = wm;
         if (first) hno[t] = wj;
         if (last) hpo[HV - 1 - t] = wm;
-        o.phi += cxc * (wm - wj);
-        o.gg += gj * gj;
-        o.gg += gm * gm;
+        o.phi += (double)(cxc * (wm - wj));
+        o.gg += (double)(gj * gj + gm * gm);
         keep(o.Sx);
         keep(o.phi);
         keep(o.gg);
@@ -880,14 +880,14 @@ __global__ void __launch_bounds__(kFineBlock) k_fine(const FineUnit *__restrict_
                 c.aeps = kv ? ar * epsr : Real(0);
                 c.aJ = kv ? (Real)((double)ar * J) : Real(0);
                 const RowOut<Real> o = pass(k, i, iv, seg, segn, segp, last, c);
-                const Real c1n = c.aeps * (o.Sx * dvR);
+                const Real c1n = (Real)((double)c.aeps * (o.Sx * dv));
                 if constexpr (RES) {
                     if (valid) s_c1[npar * nx + i] = c1n;
                 } else {
                     C1[(size_t)npar * ld + i] = c1n;
                 }
-                if (kv) Phi = -((double)o.phi * dx) * dv;
-                Nn = epsr * (Real)sqrt((double)(o.gg * dvR));
+                if (kv) Phi = -(o.phi * dx) * dv;
+                Nn = (Real)((double)epsr * sqrt(o.gg * dv));
             }
             if (valid) {
                 s_phi[i] = Phi;

@@ -1,0 +1,68 @@
+"""Serving loop: admission bookkeeping (CPU) and continuous batching on the
+GPU, where every served result equals the same solve alone, bit for bit."""
+import numpy as np
+import pytest
+
+from paper_2511_13386_amd import serving, sth
+from paper_2511_13386_amd import workloads as wl
+
+from helpers import desc_of
+
+
+def test_free_list_first_fit_and_coalescing():
+    fl = serving.FreeList(10_000)
+    assert fl.nbytes == 9984  # whole 256-byte blocks
+    a = fl.alloc(1000)
+    b = fl.alloc(300)
+    c = fl.alloc(256)
+    assert (a, b, c) == (0, 1024, 1536)
+    assert fl.alloc(9000) is None
+    fl.release(b, 300)
+    assert fl.alloc(200) == 1024        # first fit reuses the hole
+    fl.release(1024, 200)
+    fl.release(a, 1000)
+    fl.release(c, 256)
+    assert fl.free == [[0, 9984]]       # everything merged back
+    with pytest.raises(ValueError):
+        fl.release(0, 256)              # double release is caught
+
+
+def test_free_list_admission_order_under_pressure():
+    fl = serving.FreeList(4096)
+    blocks = [fl.alloc(1024) for _ in range(4)]
+    assert blocks == [0, 1024, 2048, 3072]
+    assert fl.alloc(1) is None
+    fl.release(1024, 1024)
+    fl.release(2048, 1024)
+    assert fl.alloc(2048) == 1024       # adjacent holes coalesce
+
+
+@pytest.mark.gpu
+def test_served_results_equal_solves_alone():
+    """Six requests of different sizes and precisions arrive staggered and
+    overlap on the device (an arena small enough that some must wait for
+    memory); each served result equals its solve alone."""
+    torch = pytest.importorskip("torch")
+    insts = [
+        (wl.small_hybrid(seed=1, nx=96, nv=32, N=3, T=2e-3, K=2), sth.FP64),
+        (wl.random_instance(11, N=4, T=1e-3, nx_choices=(128,), nv_choices=(64,)), sth.FP32_BULK),
+        (wl.random_instance(12, N=3, T=1e-3, nx_choices=(256,), nv_choices=(32,)), sth.FP64),
+        (wl.random_instance(13, N=2, T=1e-3, nx_choices=(512,), nv_choices=(128,)), sth.FP32_BULK),
+        (wl.random_instance(14, N=4, T=1e-3, nx_choices=(128,), nv_choices=(32,)), sth.FP64),
+        (wl.random_instance(15, N=3, T=1e-3, nx_choices=(1024,), nv_choices=(64,)), sth.FP32_BULK),
+    ]
+    descs = [desc_of(i, precision=p, K=2) for i, p in insts]
+    sizes = [sth.sth_footprint_bytes(d) for d in descs]
+    budget = sum(sorted(sizes)[-3:]) + 4096  # not all fit at once
+    srv = serving.Server(budget)
+    reqs = [serving.Request(r, d, 0.002 * r, max_iters=2) for r, d in enumerate(descs)]
+    res = srv.run(reqs)
+    assert srv.ticks >= 3
+    assert srv.arena.free_bytes == srv.arena.nbytes
+    for r, d in zip(res, descs):
+        p = sth.Problem(d)
+        sth.parareal_solve(p, K=2, fixed_iterations=True)
+        assert np.array_equal(r.rho, sth.sth_get_rho(p))
+        assert r.latency > 0 and r.finished >= r.admitted >= 0
+        p.close()
+    torch.cuda.synchronize()

@@ -84,7 +84,7 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--workload", choices=["config2", "batch", "serve"], default="config2",
+    ap.add_argument("--workload", choices=["config2", "batch", "serve", "convergence"], default="config2",
                     help="config2: the hybrid parareal problem the metric is quoted on; "
                          "batch: many independent instances in one batched sweep per iteration")
     ap.add_argument("--batch-count", type=int, default=256)
@@ -313,6 +313,40 @@ def run_serve(args, torch, sth, wl):
     print(json.dumps(out), flush=True)
 
 
+def run_convergence(args, torch, sth, wl):
+    """Parareal iterations to a successive error of 1e-10 against eps, with
+    and without domain adaptation, in the paper's Section 5 setting (1D1V):
+    the convergence study of the paper's Section 5.1."""
+    eps_list = [1e-7, 1e-6, 1e-5, 1e-4, 1e-3, 1e-2, 1e-1, 0.5, 1.0]
+    rows = []
+    t0 = time.perf_counter()
+    for mode, mode_name, L in ((sth.START_LIFT, "lift", 3), (sth.START_LIFT, "lift", 1),
+                               (sth.START_CARRY, "carry", 1)):
+        for adapt in (False, True):
+            for eps in eps_list:
+                inst = wl.paper_setting(eps, adaptation=adapt, lift_order=L)
+                d = sth.Desc(nx=inst.nx, nv=inst.nv, eps_iface=inst.eps_iface, eps_cell=inst.eps_cell,
+                             rho0=inst.rho_in, T=inst.T, n_slices=inst.N, k_max=inst.N, tol=inst.tol,
+                             eta0=inst.eta0, delta0=inst.delta0, lift_order=inst.lift_order,
+                             start_mode=mode, cfl_theta=inst.theta,
+                             flags=sth.FIELD | (sth.HYBRID if adapt else 0), Lx=inst.Lx, vstar=inst.vstar)
+                p = sth.Problem(d)
+                errs = sth.parareal_solve(p, K=inst.N, tol=inst.tol)
+                info = p.info()
+                rows.append({"start": mode_name, "lift_order": L, "adaptation": adapt, "eps": eps,
+                             "iterations": len(errs),
+                             "final_err": errs[-1], "steps_per_slice": info.steps_per_slice,
+                             "kinetic_fraction": info.kinetic_iface_steps / max(
+                                 1.0, inst.nx * info.steps_per_slice * sum(inst.N - k for k in range(len(errs))))})
+                p.close()
+    out = {"metric": "parareal iterations to successive error 1e-10 (convergence study)",
+           "value": None, "unit": "iterations", "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": "paper Section 5 setting in 1D1V: Nx=Nv=32, x*=2pi, v*=8, N_g=200, T_f=1, "
+                                  "eta0=delta0=1e-5, rho_in=3(1+0.9cos x), g'=0; slice starts lifted (L=3, L=1) or carried"},
+           "runs": rows, "wall_s": time.perf_counter() - t0}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -332,6 +366,9 @@ def main():
         return
     if args.workload == "serve":
         run_serve(args, torch, sth, wl)
+        return
+    if args.workload == "convergence":
+        run_convergence(args, torch, sth, wl)
         return
     prec = sth.FP64 if args.precision == "fp64" else sth.FP32_BULK
     inst = wl.config2(seed=args.seed, nx=args.nx, nv=args.nv, N=args.slices, T=args.T,

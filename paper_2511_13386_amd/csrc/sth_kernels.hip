@@ -159,7 +159,7 @@ __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(
 
 // LDS layout of the fine kernel.  Same function on host (sizing) and device.
 struct FineLds {
-    size_t rho, jc, phi, E, nrm, cm, crit, tot, wtot, jtot, c1, halo, total;
+    size_t rho, jc, phi, E, nrm, cm, crit, tot, wtot, jtot, dummy, c1, halo, total;
 };
 // res: the resident kernel, which also keeps the lazy projection c1[2][nx]
 // and the halo rows [2 parity][2 side][nseg][nv/2] in LDS.
@@ -179,6 +179,7 @@ __host__ __device__ inline FineLds fine_lds(int nx, int nv, int realsz, int nslo
     L.tot = o;  o = align16(o + sizeof(double) * nslot);
     L.wtot = o; o = align16(o + sizeof(double) * nslot);
     L.jtot = o; o = align16(o + sizeof(double) * nslot);
+    L.dummy = o; o = align16(o + (sizeof(double) + 1) * kWave);  // per-lane sink of ghost writes
     L.c1 = o;   if (res) o = align16(o + (size_t)realsz * 2 * nx);
     L.halo = o; if (res) o = align16(o + (size_t)realsz * 2 * 2 * ((nx + kWave - 1) / kWave) * (nv / 2));
     L.total = o;
@@ -320,8 +321,10 @@ struct RowIO {
 // chunks per half, and a rolled chunk loop wherever the grid has more than
 // two chunks (a straight run of chunks lets the compiler stretch live
 // ranges across them).
-template <int NV>
-constexpr int pair_chunk_len() { return NV == 32 ? 2 : 4; }
+// FP32 rows take half the registers, so their chunks are twice as long
+// (twice the loads in flight) on the wider grids.
+template <typename Real, int NV>
+constexpr int pair_chunk_len() { return NV == 32 ? 2 : (NV >= 64 && sizeof(Real) == 4 ? 8 : 4); }
 template <typename Real, int CH>
 struct PairBuf {
     Real wn[CH], wp[CH], hn[CH], hp[CH];
@@ -410,7 +413,7 @@ template <typename Real, int NV, bool RAGGED>
 __device__ __forceinline__ RowOut<Real> row_pass(const RowIO &io, const RowCoef<Real> &c, bool first, bool last,
                                                  ConstPtr<Real> vt)
 {
-    constexpr int HV = NV / 2, CH = pair_chunk_len<NV>();
+    constexpr int HV = NV / 2, CH = pair_chunk_len<Real, NV>();
     constexpr unsigned R = sizeof(Real);
     RowOut<Real> o{0, 0, 0};
     PairBuf<Real, CH> A, B;
@@ -553,20 +556,24 @@ __global__ void __launch_bounds__(kFineBlock) k_fine(const FineUnit *__restrict_
     unsigned char *s_cm = (unsigned char *)(smem + L.cm);      // [2][nx+1] cell status by step parity
     unsigned char *s_crit = (unsigned char *)(smem + L.crit);  // [nx+1] remainder criterion
     const int ncm = nx + 1;
+    // Ghost copies are written without branches: a lane whose cell has no
+    // ghost writes its second copy to its own slot of a sink array.
+    double *s_sink = (double *)(smem + L.dummy);
+    unsigned char *s_sink8 = (unsigned char *)(s_sink + kWave);
     auto put_rho = [&](int i, double v) {
         s_rho[i] = v;
-        if (i < 3) s_rho[nx + i] = v;
-        if (i >= nx - 3) s_rho[i - nx] = v;
+        double *g = i < 3 ? s_rho + nx + i : (i >= nx - 3 ? s_rho + (i - nx) : s_sink + lane);
+        *g = v;
     };
     auto put_jc = [&](int i, double v) {
         s_jc[i] = v;
-        if (i < 3) s_jc[nx + i] = v;
-        if (i >= nx - 3) s_jc[i - nx] = v;
+        double *g = i < 3 ? s_jc + nx + i : (i >= nx - 3 ? s_jc + (i - nx) : s_sink + lane);
+        *g = v;
     };
     auto put_nrm = [&](int i, Real v) {
         s_nrm[i] = v;
-        if (i == 0) s_nrm[nx] = v;
-        if (i == nx - 1) s_nrm[-1] = v;
+        Real *g = i == 0 ? s_nrm + nx : (i == nx - 1 ? s_nrm - 1 : (Real *)(s_sink + lane));
+        *g = v;
     };
     double *s_tot = (double *)(smem + L.tot);
     double *s_wtot = (double *)(smem + L.wtot);
@@ -745,7 +752,7 @@ __global__ void __launch_bounds__(kFineBlock) k_fine(const FineUnit *__restrict_
                 const double ec = g_epsc[i];
                 const double crit = literal ? fabs(R) : ec * ec * fabs(R);
                 s_crit[i] = (unsigned char)(crit > eta0);
-                if (i == 0) s_crit[nx] = (unsigned char)(crit > eta0);
+                *(i == 0 ? s_crit + nx : s_sink8 + lane) = (unsigned char)(crit > eta0);
             }
         }
     };
@@ -762,12 +769,14 @@ __global__ void __launch_bounds__(kFineBlock) k_fine(const FineUnit *__restrict_
         for (int k = 0; k < IPTM; ++k) {
             const int i = k * BS + tid;
             if (k < ipt && i < nx) {
+                // every input read up front, combined without short-circuits
                 const double Nm = (double)s_nrm[i - 1], N0 = (double)s_nrm[i], Np = (double)s_nrm[i + 1];
+                const unsigned cr0 = s_crit[i], cr1 = s_crit[i + 1], co0 = cm_old[i], co1 = cm_old[i + 1];
                 const double n0 = Nm > N0 ? Nm : N0, n1 = N0 > Np ? N0 : Np;
-                const int ci = s_crit[i] || (cm_old[i] && n0 > delta0);
-                const int cn = s_crit[i + 1] || (cm_old[i + 1] && n1 > delta0);
+                const int ci = (int)(cr0 | (co0 & (n0 > delta0 ? 1u : 0u)));
+                const int cn = (int)(cr1 | (co1 & (n1 > delta0 ? 1u : 0u)));
                 s_cm[par * ncm + i] = (unsigned char)ci;
-                if (i == 0) s_cm[par * ncm + nx] = (unsigned char)ci;
+                *(i == 0 ? s_cm + par * ncm + nx : s_sink8 + lane) = (unsigned char)ci;
                 cmbits = (cmbits & ~(1u << k)) | ((unsigned)ci << k);
                 const int kn = ci | cn;
                 if (((kinbits >> k) & 1u) && !kn) {
@@ -891,7 +900,7 @@ __global__ void __launch_bounds__(kFineBlock) k_fine(const FineUnit *__restrict_
             }
             if (valid) {
                 s_phi[i] = Phi;
-                if (i == nx - 1) s_phi[-1] = Phi;
+                *(i == nx - 1 ? s_phi - 1 : s_sink + lane) = Phi;
                 put_nrm(i, Nn);
             }
         };

@@ -159,6 +159,22 @@ def poisson_arrivals(n: int, rate: float, seed: int = 99) -> np.ndarray:
     return np.cumsum(gaps)
 
 
+def paper_setting(eps: float, adaptation: bool = True, nx: int = 32, nv: int = 32, N: int = 200,
+                  T: float = 1.0, lift_order: int = 3) -> Instance:
+    """The numerical setting of the paper's Section 5 in 1D1V: torus length
+    2 pi, v* = 8, Nx = Nvx = 32, N_g = 200 slices, T_f = 1, thresholds
+    eta0 = delta0 = 1e-5, lifting order 3, constant eps.  Initial density
+    3 (1 + 0.9 cos(x)), the density of the paper's far-from-equilibrium
+    initial condition (<v^4 M> = 3), started at local equilibrium (g' = 0)."""
+    Lx = 2 * math.pi
+    xc = cell_centres(nx, Lx)
+    return Instance(nx=nx, nv=nv, rho_in=3.0 * (1.0 + 0.9 * np.cos(2 * math.pi * xc / Lx)),
+                    eps_iface=np.full(nx, eps), eps_cell=np.full(nx, eps), T=T, N=N, K=N,
+                    tol=1e-10, theta=1.0, vstar=8.0, Lx=Lx, eta0=1e-5, delta0=1e-5,
+                    hybrid=adaptation, lift_order=lift_order,
+                    name=f"paper-setting-eps{eps:.0e}-{'adapt' if adaptation else 'noadapt'}")
+
+
 def small_hybrid(seed: int = 0, nx: int = 96, nv: int = 32, N: int = 4, T: float = 2e-3,
                  K: int = 4) -> Instance:
     """A small hybrid instance with the tanh eps profile: oracle-sized (seconds)

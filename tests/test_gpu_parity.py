@@ -170,6 +170,27 @@ def test_full_size_sample_config3_fp64(orc):
     assert rel_err(gg, go) < G64
 
 
+@pytest.mark.parametrize("eps,L,mode", [(1e-6, 3, "lift"), (1e-2, 3, "lift"), (1.0, 1, "lift"),
+                                         (1e-1, 1, "carry")])
+def test_convergence_study_setting(orc, eps, L, mode):
+    """The paper's Section 5 setting in 1D1V (N_g = 200, tol 1e-10, adaptation
+    on): the GPU takes the same number of parareal iterations as the oracle
+    and reaches the same slice-end densities."""
+    inst = wl.paper_setting(eps, adaptation=True, lift_order=L)
+    smode = sth.START_LIFT if mode == "lift" else sth.START_CARRY
+    omode = orc.START_LIFT if mode == "lift" else orc.START_CARRY
+    p = sth.Problem(desc_of(inst, start_mode=smode, K=inst.N))
+    errs = sth.parareal_solve(p, K=inst.N, tol=inst.tol)
+    U = sth.sth_get_rho(p)
+    p.close()
+    po, ns, dtG = oracle_of(orc, inst, start_mode=omode)
+    Uo, erro, it, _ = orc.parareal(po, inst.eps_iface, inst.eps_cell, inst.N, ns, dtG, inst.N, inst.tol,
+                                   inst.rho_in)
+    assert len(errs) == it
+    assert errs[-1] < inst.tol
+    assert rel_err(U, Uo) < 1e-11
+
+
 def test_diagnostics_match_oracle(orc):
     inst = wl.small_hybrid(nx=80, nv=32, N=2, T=1e-3)
     p = sth.Problem(desc_of(inst, K=2))

@@ -45,6 +45,19 @@ extern "C" {
 #define STH_FIELD      2   /* self-consistent field; off means E == 0         */
 #define STH_LITERAL_R  4   /* macroscopic criterion on |R| as printed instead
                               of eps^2 |R|                                    */
+#define STH_COARSE_EXPLICIT 16 /* coarse propagator G = the explicit limit
+                              scheme S^0 (Section 3.3) in ceil(dtG / (0.75
+                              cfl_theta dx^2/(2 m2))) steps per interval;
+                              default: one backward-Euler drift-diffusion
+                              step with the field frozen at the interval
+                              start                                         */
+#define STH_LITERAL_FLUX 8 /* density update of scheme S^HMM cell by cell as
+                              printed (Section 2.3): kinetic cells take the
+                              kinetic fluxes of both interfaces, fluid cells
+                              the limit fluxes m2 J; not conservative where
+                              the two meet.  Default: flux-matched (each
+                              interface one flux, kinetic iff the interface is
+                              kinetic), which conserves mass exactly.        */
 
 /* precision */
 #define STH_FP64       0   /* everything in float64                           */
@@ -80,7 +93,8 @@ typedef struct {
     int           lift_order;  /* L in {1, 2, 3}                               */
     int           start_mode;  /* STH_START_*                                  */
     double        cfl_theta;   /* fraction of the stable fine step, (0, 1]     */
-    int           flags;       /* STH_HYBRID | STH_FIELD | STH_LITERAL_R       */
+    int           flags;       /* STH_HYBRID | STH_FIELD | STH_LITERAL_R |
+                                  STH_LITERAL_FLUX | STH_COARSE_EXPLICIT      */
     int           precision;   /* STH_FP64 or STH_FP32_BULK                    */
     long long     steps_override; /* > 0 forces the fine steps per slice       */
 } sth_problem_desc;
@@ -100,6 +114,8 @@ typedef struct {
     int       fine_resident;   /* 1: the fine sweep keeps the rows of a slice
                                   in registers; 0: streamed every step       */
     int       fine_block;      /* threads per fine-sweep workgroup            */
+    long long coarse_steps;    /* steps of the coarse scheme per interval:
+                                  1, or that of STH_COARSE_EXPLICIT           */
 } sth_info;
 
 /* Device bytes a problem with this description needs (serving admission).

@@ -8,6 +8,7 @@ phase-space arrays are x-major ``g[p, j]``.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -20,6 +21,8 @@ _LIB = os.path.join(_HERE, "libsth_oracle.so")
 HYBRID = 1
 FIELD = 2
 LITERAL_R = 4
+LITERAL_FLUX = 8
+COARSE_EXPLICIT = 16
 START_LIFT = 0
 START_CARRY = 1
 
@@ -43,6 +46,7 @@ class Params(ctypes.Structure):
         ("eta0", ctypes.c_double), ("delta0", ctypes.c_double),
         ("flags", ctypes.c_int), ("lift_order", ctypes.c_int),
         ("start_mode", ctypes.c_int),
+        ("coarse_steps", ctypes.c_long),
     ]
 
 
@@ -282,6 +286,9 @@ def setup(nx, nv, eps_iface, rho_in, *, T, N, theta=1.0, Lx=1.0, vstar=8.0, eta0
     dtm = dt_max(p, eps_iface, Emax, theta)
     ns, dt = steps_per_slice(T / N, dtm)
     p.dt = dt
+    # explicit coarse scheme: its diffusive stable step with the same margin
+    m2 = velocity_grid(nv, vstar)[2]
+    p.coarse_steps = int(math.ceil((T / N) / (theta * 0.75 * dx * dx / (2.0 * m2))))
     return p, ns, T / N
 
 

@@ -447,8 +447,19 @@ void orc_fine_propagate(const orc_params *p, const double *eps_iface, const doub
             Phi[q] = -flux;
         }
 
-        /* 4. conservative density update */
-        for (int i = 0; i < nx; ++i) rho[i] = rho[i] + dt / dx * (Phi[i] - Phi[wrap(i - 1, nx)]);
+        /* 4. density update: flux-matched (conservative), or cell-wise as
+         *    printed in scheme S^HMM (kinetic cells: kinetic fluxes; fluid
+         *    cells: limit fluxes m2 J), with the cell status of time n */
+        if (hybrid && (p->flags & ORC_LITERAL_FLUX)) {
+            for (int i = 0; i < nx; ++i) {
+                int im = wrap(i - 1, nx);
+                double fr = cell[i] ? Phi[i] : m2 * J[i];
+                double fl = cell[i] ? Phi[im] : m2 * J[im];
+                rho[i] = rho[i] + dt / dx * (fr - fl);
+            }
+        } else {
+            for (int i = 0; i < nx; ++i) rho[i] = rho[i] + dt / dx * (Phi[i] - Phi[wrap(i - 1, nx)]);
+        }
 
         /* 5. new status; fluid interfaces hold g' = 0 */
         if (hybrid) {
@@ -528,8 +539,35 @@ int orc_cyclic_tridiag(int n, const double *a, const double *b, const double *c,
  * followed by the conservative form rho^{n+1} = rho^n + dtG L_E rho~, which
  * equals rho~ in exact arithmetic and telescopes in floating point.
  * ------------------------------------------------------------------------- */
+/* explicit limit scheme S^0 (Section 2.3): nsteps steps of
+ *   rho_i <- rho_i + dt/dx (m2 J_{i+1/2} - m2 J_{i-1/2}),
+ * J from the current rho and its Gauss-law field (the fluid fluxes of the
+ * fine scheme, in the same order of operations) */
+static void limit_scheme(const orc_params *p, double dt, long nsteps, const double *rho_in, double *rho_out)
+{
+    int nx = p->nx, field = (p->flags & ORC_FIELD) != 0;
+    double dx = p->Lx / nx;
+    double *v = malloc(sizeof(double) * p->nv), *M = malloc(sizeof(double) * p->nv), m2;
+    orc_velocity_grid(p->nv, p->vstar, v, M, &m2);
+    double *E = calloc(nx, sizeof(double)), *J = malloc(sizeof(double) * nx);
+    double *Phi = malloc(sizeof(double) * nx);
+    memcpy(rho_out, rho_in, sizeof(double) * nx);
+    for (long n = 0; n < nsteps; ++n) {
+        if (field) orc_poisson(nx, dx, rho_out, p->rhobar, E);
+        orc_flux_J(nx, dx, rho_out, E, J);
+        for (int q = 0; q < nx; ++q) Phi[q] = m2 * J[q];
+        for (int i = 0; i < nx; ++i) rho_out[i] = rho_out[i] + dt / dx * (Phi[i] - Phi[wrap(i - 1, nx)]);
+    }
+    free(v); free(M); free(E); free(J); free(Phi);
+}
+
 void orc_coarse_step(const orc_params *p, double dtG, const double *rho_in, double *rho_out)
 {
+    if (p->flags & ORC_COARSE_EXPLICIT) {
+        long ns = p->coarse_steps > 0 ? p->coarse_steps : 1;
+        limit_scheme(p, dtG / (double)ns, ns, rho_in, rho_out);
+        return;
+    }
     int nx = p->nx, field = (p->flags & ORC_FIELD) != 0;
     double dx = p->Lx / nx;
     double *v = malloc(sizeof(double) * p->nv), *M = malloc(sizeof(double) * p->nv), m2;

@@ -33,6 +33,15 @@ extern "C" {
 #define ORC_HYBRID   1  /* dynamic domain adaptation on (Section 2.2/2.3)      */
 #define ORC_FIELD    2  /* self-consistent field on; off means E == 0          */
 #define ORC_LITERAL_R 4 /* criterion on |R| as printed instead of eps^2 |R|    */
+#define ORC_COARSE_EXPLICIT 16 /* coarse propagator G = the explicit limit
+                              scheme S^0 (Section 3.3) in coarse_steps steps
+                              per coarse interval; default: one backward-Euler
+                              drift-diffusion step                           */
+#define ORC_LITERAL_FLUX 8 /* cell-wise density update of scheme S^HMM as
+                              printed: a kinetic cell takes the kinetic fluxes
+                              of its two interfaces, a fluid cell the limit
+                              fluxes m2 J (not conservative where the two kinds
+                              of cells meet); default: flux-matched            */
 
 /* slice-start perturbation of the parareal fine sweeps */
 #define ORC_START_LIFT  0 /* lifting L^L of the slice-start density (Algorithm 1) */
@@ -49,6 +58,7 @@ typedef struct {
     int    flags;       /* ORC_* bits                                         */
     int    lift_order;  /* L in {1,2,3} for the lifting operator              */
     int    start_mode;  /* ORC_START_* for the parareal slice starts          */
+    long   coarse_steps; /* steps of S^0 per coarse interval (ORC_COARSE_EXPLICIT) */
 } orc_params;
 
 typedef struct {
@@ -94,7 +104,9 @@ void   orc_fine_propagate(const orc_params *p, const double *eps_iface, const do
                           const double *rho_in, const double *g_in, long nsteps,
                           double *rho_out, double *g_out, int *cell_mask_out, orc_stats *st);
 
-/* one backward-Euler drift-diffusion step with frozen field (coarse G) */
+/* coarse G over one interval dtG: one backward-Euler drift-diffusion step
+ * with frozen field, or (ORC_COARSE_EXPLICIT) coarse_steps steps of the
+ * explicit limit scheme S^0 */
 void   orc_coarse_step(const orc_params *p, double dtG, const double *rho_in, double *rho_out);
 
 /* cyclic tridiagonal solve: a_i x_{i-1} + b_i x_i + c_i x_{i+1} = d_i (mod n) */

@@ -90,7 +90,8 @@ int validate(const sth_problem_desc *d)
     if (!(d->cfl_theta > 0) || d->cfl_theta > 1) return fail(STH_EINVAL, "cfl_theta must be in (0, 1]");
     if (d->precision != STH_FP64 && d->precision != STH_FP32_BULK)
         return fail(STH_EINVAL, "unknown precision");
-    if (d->flags & ~(STH_HYBRID | STH_FIELD | STH_LITERAL_R)) return fail(STH_EINVAL, "unknown flags");
+    if (d->flags & ~(STH_HYBRID | STH_FIELD | STH_LITERAL_R | STH_LITERAL_FLUX | STH_COARSE_EXPLICIT))
+        return fail(STH_EINVAL, "unknown flags");
     if (fine_shape(d->precision == STH_FP64 ? 0 : 1, d->nx, d->nv, 0, 0).lds > kMaxLds)
         return fail(STH_EINVAL, "unit too large for one workgroup's LDS");
     return STH_OK;
@@ -162,7 +163,7 @@ int side_pool(SidePool **out)
 struct sth_problem {
     int nx, nv, N, K, prec, realsz, flags, start_mode, lift_order;
     double Lx, vstar, T, tol, dx, dv, dt, dtG, m2, rhobar, eta0, delta0;
-    long long ns;
+    long long ns, coarse_steps = 1;
     char *base = nullptr;
     size_t bytes = 0;
     bool owned = false;
@@ -371,6 +372,10 @@ int sth_create(const sth_problem_desc *d, void *arena, size_t arena_bytes, sth_p
     c.nx = nx; c.nv = nv; c.flags = d->flags;
     c.dx = p->dx; c.dv = p->dv; c.dt = p->dt; c.rhobar = p->rhobar; c.m2 = p->m2;
     c.eta0 = d->eta0; c.delta0 = d->delta0; c.nsteps = ns;
+    // explicit coarse scheme: its diffusive stable step with the fine step's margin
+    c.coarse_steps = (long long)std::ceil(p->dtG / (d->cfl_theta * 0.75 * p->dx * p->dx / (2.0 * p->m2)));
+    if (c.coarse_steps < 1) c.coarse_steps = 1;
+    p->coarse_steps = c.coarse_steps;
     c.eps_p = p->at<double>(p->L.eps_p);
     c.eps_c = p->at<double>(p->L.eps_c);
     c.e_p = p->at<double>(p->L.e_p);
@@ -442,7 +447,7 @@ int sth_coarse_sweep(sth_problem *p, void *stream)
     j.N = p->N;
     j.mode = 0;
     j.k = 0;
-    HIPCHK(launch_coarse(j, p->nx, (hipStream_t)stream));
+    HIPCHK(launch_coarse(j, p->nx, (p->flags & STH_COARSE_EXPLICIT) != 0, (hipStream_t)stream));
     p->coarse_done = true;
     p->k = 0;
     p->swept = false;
@@ -588,7 +593,7 @@ int sth_parareal_correct(sth_problem *p, double *err_out, int *k_out, void *stre
     j.N = p->N;
     j.mode = 1;
     j.k = p->k;
-    HIPCHK(launch_coarse(j, p->nx, st));
+    HIPCHK(launch_coarse(j, p->nx, (p->flags & STH_COARSE_EXPLICIT) != 0, st));
     p->k += 1;
     p->swept = false;
     if (err_out) {
@@ -669,6 +674,7 @@ int sth_get_info(const sth_problem *p, sth_info *out)
     const FineShape sh = fine_shape(p->prec, p->nx, p->nv, 0, 0);
     out->fine_resident = sh.stream ? 0 : 1;
     out->fine_block = sh.block;
+    out->coarse_steps = (p->flags & STH_COARSE_EXPLICIT) ? p->coarse_steps : 1;
     return STH_OK;
 }
 

@@ -20,6 +20,7 @@ struct FineConst {
     int pad0;
     double dx, dv, dt, rhobar, m2, eta0, delta0;
     long long nsteps;     // fine steps per slice
+    long long coarse_steps; // steps of S^0 per coarse interval (STH_COARSE_EXPLICIT)
     const double *eps_p;  // [nx] eps at interfaces
     const double *eps_c;  // [nx] eps at cell centres
     const double *e_p;    // [nx] exp(-dt/eps_p^2)
@@ -93,7 +94,7 @@ struct CoarseJob {
     int mode;             // 0 = coarse guess, 1 = correction
     int k;                // iteration index (correction)
 };
-hipError_t launch_coarse(const CoarseJob &job, int nx, hipStream_t st);
+hipError_t launch_coarse(const CoarseJob &job, int nx, bool explicit_scheme, hipStream_t st);
 
 // Diagnostics of a state (rho, g).
 struct DiagJob {

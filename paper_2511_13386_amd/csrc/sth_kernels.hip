@@ -159,7 +159,7 @@ __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(
 
 // LDS layout of the fine kernel.  Same function on host (sizing) and device.
 struct FineLds {
-    size_t rho, jc, phi, E, nrm, cm, crit, tot, wtot, jtot, dummy, c1, halo, total;
+    size_t rho, jc, phi, phiJ, E, nrm, cm, crit, tot, wtot, jtot, dummy, c1, halo, total;
 };
 // res: the resident kernel, which also keeps the lazy projection c1[2][nx]
 // and the halo rows [2 parity][2 side][nseg][nv/2] in LDS.
@@ -172,6 +172,7 @@ __host__ __device__ inline FineLds fine_lds(int nx, int nv, int realsz, int nslo
     L.rho = o;  o = align16(o + sizeof(double) * (nx + 6));
     L.jc = o;   o = align16(o + sizeof(double) * (nx + 6));
     L.phi = o;  o = align16(o + sizeof(double) * (nx + 1));
+    L.phiJ = o; o = align16(o + sizeof(double) * (nx + 1));
     L.E = o;    o = align16(o + sizeof(double) * nx);
     L.nrm = o;  o = align16(o + (size_t)realsz * (nx + 2));
     L.cm = o;   o = align16(o + sizeof(unsigned char) * 2 * (nx + 1));
@@ -539,6 +540,7 @@ __global__ void __launch_bounds__(kFineBlock) k_fine(const FineUnit *__restrict_
     const int nslot = ipt * NW;
     const int flags = C->flags;
     const bool hybrid = flags & STH_HYBRID, field = flags & STH_FIELD, literal = flags & STH_LITERAL_R;
+    const bool cellwise = hybrid && (flags & STH_LITERAL_FLUX);
     const long long nsteps = U.nsteps > 0 ? U.nsteps : C->nsteps;
     const double *__restrict__ g_e = C->e_p;
     const double *__restrict__ g_a = C->a_p;
@@ -551,6 +553,7 @@ __global__ void __launch_bounds__(kFineBlock) k_fine(const FineUnit *__restrict_
     double *s_rho = (double *)(smem + L.rho) + 3;
     double *s_jc = (double *)(smem + L.jc) + 3;
     double *s_phi = (double *)(smem + L.phi) + 1;
+    double *s_phiJ = (double *)(smem + L.phiJ) + 1;  // m2 J per interface (cell-wise update)
     double *s_E = (double *)(smem + L.E);
     Real *s_nrm = (Real *)(smem + L.nrm) + 1;  // eps ||g|| of the last pass
     unsigned char *s_cm = (unsigned char *)(smem + L.cm);      // [2][nx+1] cell status by step parity
@@ -820,15 +823,21 @@ __global__ void __launch_bounds__(kFineBlock) k_fine(const FineUnit *__restrict_
             }
         }
     };
-    // Conservative density update with the fluxes of the previous step,
-    // compensated (Kahan) so that long slices keep the mass to round-off.
-    auto density_update = [&]() {
+    // Density update with the fluxes of the previous step, compensated
+    // (Kahan) so that long slices keep the mass to round-off: flux-matched
+    // (conservative), or cell-wise as printed in scheme S^HMM with the cell
+    // status cm of the previous step (kinetic cell: kinetic fluxes, fluid
+    // cell: m2 J).
+    auto density_update = [&](unsigned cm) {
 #pragma unroll
         for (int k = 0; k < IPTM; ++k) {
             const int i = k * BS + tid;
             if (k < ipt && i < nx) {
                 const double r = s_rho[i];
-                const double y = dtdx * (s_phi[i] - s_phi[i - 1]) - comp[k];
+                const bool kin_cell = !cellwise || ((cm >> k) & 1u);
+                const double fr = kin_cell ? s_phi[i] : s_phiJ[i];
+                const double fl = kin_cell ? s_phi[i - 1] : s_phiJ[i - 1];
+                const double y = dtdx * (fr - fl) - comp[k];
                 const double t = r + y;
                 comp[k] = (t - r) - y;
                 put_rho(i, t);
@@ -852,8 +861,9 @@ __global__ void __launch_bounds__(kFineBlock) k_fine(const FineUnit *__restrict_
         tid = opaque_v(tid);
         lane = tid & (kWave - 1);
         // P1: status of step n, density at step n, prefix sums.
+        const unsigned cm_prev = cmbits;
         if (hybrid) status(par);
-        if (n > 0) density_update();
+        if (n > 0) density_update(cm_prev);
         macro_scan();
         __syncthreads();  // B1
         // P2: field and cell-centred flux.
@@ -901,6 +911,10 @@ __global__ void __launch_bounds__(kFineBlock) k_fine(const FineUnit *__restrict_
             if (valid) {
                 s_phi[i] = Phi;
                 *(i == nx - 1 ? s_phi - 1 : s_sink + lane) = Phi;
+                if (cellwise) {
+                    s_phiJ[i] = m2 * J;
+                    *(i == nx - 1 ? s_phiJ - 1 : s_sink + lane) = m2 * J;
+                }
                 put_nrm(i, Nn);
             }
         };
@@ -957,8 +971,9 @@ __global__ void __launch_bounds__(kFineBlock) k_fine(const FineUnit *__restrict_
 
     // ---------------------------------------------------------- epilogue
     const int fpar = (int)(nsteps & 1);
+    const unsigned cm_last = cmbits;
     if (hybrid) status(fpar);
-    if (nsteps > 0) density_update();
+    if (nsteps > 0) density_update(cm_last);
 #pragma unroll
     for (int k = 0; k < IPTM; ++k) {
         const int i = k * BS + tid;
@@ -1272,6 +1287,78 @@ __device__ void coarse_step_block(const FineConst *C, const double *rin, double 
     __syncthreads();
 }
 
+// Explicit limit scheme S^0 (Section 2.3, the paper's coarse propagator of
+// Section 3.3) over one coarse interval: coarse_steps steps of
+// rho_i += dt/dx m2 (J_{i+1/2} - J_{i-1/2}) with J from the current rho and
+// its Gauss-law field.  One workgroup; rho and the fluxes in dynamic LDS;
+// each thread owns nx/blockDim contiguous cells, and the Gauss-law prefix
+// sums are DPP wavefront scans plus a pass over the wave totals.
+__device__ void coarse_explicit_block(const FineConst *C, const double *rin, double *rout, double dtG)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int nx = C->nx, BS = blockDim.x, t = threadIdx.x, lane = t & (kWave - 1), wid = t / kWave;
+    const int NW = (BS + kWave - 1) / kWave;
+    double *r = (double *)smem;  // [nx]
+    double *phi = r + nx;        // [nx]
+    double *wt = phi + nx;       // [2][16] wave totals
+    const int q = (nx + BS - 1) / BS;  // cells per thread, at most 2
+    const long long ns = C->coarse_steps > 0 ? C->coarse_steps : 1;
+    const double dt = dtG / (double)ns, dx = C->dx, m2 = C->m2, rhobar = C->rhobar;
+    const double dtdx = dt / dx, inv_dx = 1.0 / dx, inv_nx = 1.0 / (double)nx;
+    const bool field = C->flags & STH_FIELD;
+    for (int i = t; i < nx; i += BS) r[i] = rin[i];
+    __syncthreads();
+    const int i0 = t * q;
+    for (long long n = 0; n < ns; ++n) {
+        double S[2] = {0.0, 0.0}, own = 0.0, wsum = 0.0;
+        for (int u = 0; u < q; ++u) {
+            const int i = i0 + u;
+            const double d = i < nx ? (r[i] - rhobar) * dx : 0.0;
+            own += d;
+            S[u] = own;
+            wsum += i < nx ? d * (double)(nx - i) : 0.0;
+        }
+        double a = own, b = wsum;
+        wave_scan2_f64(a, b);
+        if (lane == kWave - 1) {
+            wt[wid] = a;
+            wt[16 + wid] = b;
+        }
+        __syncthreads();
+        double off = 0.0, Wtot = 0.0;
+        for (int w = 0; w < NW; ++w) {
+            const double tw = wt[w];
+            off += w < wid ? tw : 0.0;
+            Wtot += wt[16 + w];
+        }
+        const double before = off + (a - own);  // sum of d over the cells before this thread's
+        const double mean = Wtot * inv_nx;      // mean of the prefix sums
+        for (int u = 0; u < q; ++u) {
+            const int i = i0 + u;
+            if (i < nx) {
+                const double E = field ? (before + S[u]) - mean : 0.0;
+                const double ri = r[i], rn = r[wrapi(i + 1, nx)];
+                const double Jp = (rn - ri) * inv_dx - E * 0.5 * (ri + rn);
+                phi[i] = m2 * Jp;
+            }
+        }
+        __syncthreads();
+        for (int u = 0; u < q; ++u) {
+            const int i = i0 + u;
+            if (i < nx) r[i] = r[i] + dtdx * (phi[i] - phi[wrapi(i - 1, nx)]);
+        }
+        __syncthreads();
+    }
+    for (int i = t; i < nx; i += BS) rout[i] = r[i];
+    __syncthreads();
+}
+
+__device__ void coarse_any_block(const FineConst *C, const double *rin, double *rout, double dtG, double *w)
+{
+    if (C->flags & STH_COARSE_EXPLICIT) coarse_explicit_block(C, rin, rout, dtG);
+    else coarse_step_block(C, rin, rout, dtG, w);
+}
+
 __global__ void __launch_bounds__(1024) k_coarse(CoarseJob J)
 {
     double *work = J.work;
@@ -1280,7 +1367,7 @@ __global__ void __launch_bounds__(1024) k_coarse(CoarseJob J)
     double *gn = work + 8 * slab;
     if (J.mode == 0) {
         for (int n = 1; n <= J.N; ++n) {
-            coarse_step_block(J.pc, J.U + (n - 1) * slab, J.U + n * slab, J.dtG, work);
+            coarse_any_block(J.pc, J.U + (n - 1) * slab, J.U + n * slab, J.dtG, work);
             for (int i = threadIdx.x; i < nx; i += blockDim.x) J.Gc[n * slab + i] = J.U[n * slab + i];
             __syncthreads();
         }
@@ -1296,7 +1383,7 @@ __global__ void __launch_bounds__(1024) k_coarse(CoarseJob J)
     }
     __syncthreads();
     for (int n = k + 2; n <= J.N; ++n) {
-        coarse_step_block(J.pc, J.U + (n - 1) * slab, gn, J.dtG, work);
+        coarse_any_block(J.pc, J.U + (n - 1) * slab, gn, J.dtG, work);
         for (int i = threadIdx.x; i < nx; i += blockDim.x) {
             const double g = gn[i];
             const double nv = g + (J.Fv[n * slab + i] - J.Gc[n * slab + i]);
@@ -1311,11 +1398,17 @@ __global__ void __launch_bounds__(1024) k_coarse(CoarseJob J)
     if (threadIdx.x == 0) J.err[0] = e;
 }
 
-hipError_t launch_coarse(const CoarseJob &job, int nx, hipStream_t st)
+hipError_t launch_coarse(const CoarseJob &job, int nx, bool explicit_scheme, hipStream_t st)
 {
     int b = ((nx + kWave - 1) / kWave) * kWave;
     if (b > 1024) b = 1024;
-    hipLaunchKernelGGL(k_coarse, dim3(1), dim3(b), 0, st, job);
+    const size_t lds = explicit_scheme ? sizeof(double) * (2 * (size_t)nx + 32) : 0;
+    if (lds) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_coarse, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_coarse, dim3(1), dim3(b), lds, st, job);
     return hipGetLastError();
 }
 

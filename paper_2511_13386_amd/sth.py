@@ -21,7 +21,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libsth.so")
 
 STH_OK, STH_EINVAL, STH_ENOMEM, STH_EHIP, STH_ENONFINITE, STH_ESTATE = 0, -1, -2, -3, -4, -5
-HYBRID, FIELD, LITERAL_R = 1, 2, 4
+HYBRID, FIELD, LITERAL_R, LITERAL_FLUX, COARSE_EXPLICIT = 1, 2, 4, 8, 16
 FP64, FP32_BULK = 0, 1
 START_LIFT, START_CARRY = 0, 1
 
@@ -62,6 +62,7 @@ class Info(ctypes.Structure):
         ("n_slices", ctypes.c_int), ("kinetic_iface_steps", ctypes.c_double),
         ("last_err", ctypes.c_double), ("footprint_bytes", ctypes.c_size_t),
         ("fine_resident", ctypes.c_int), ("fine_block", ctypes.c_int),
+        ("coarse_steps", ctypes.c_longlong),
     ]
 
 

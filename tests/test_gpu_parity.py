@@ -191,6 +191,30 @@ def test_convergence_study_setting(orc, eps, L, mode):
     assert rel_err(U, Uo) < 1e-11
 
 
+@pytest.mark.parametrize("precision", [sth.FP64])
+def test_cellwise_density_update_flag(orc, precision):
+    """The printed cell-wise density update (STH_LITERAL_FLUX) against the
+    oracle's: same masks, same densities, and the same (nonzero) mass
+    change where kinetic and fluid cells meet."""
+    inst = wl.small_hybrid(seed=2, nx=96, nv=32)
+    inst.rho_in = 1.0 + 0.3 * np.cos(2 * np.pi * wl.cell_centres(inst.nx))
+    d = desc_of(inst, precision=precision)
+    d.flags |= sth.LITERAL_FLUX
+    p = sth.Problem(d)
+    rg, gg, mg, kg = sth.sth_fine_run(p, inst.rho_in, None, 800)
+    p.close()
+    po, ns, _ = oracle_of(orc, inst)
+    po.flags |= orc.LITERAL_FLUX
+    ro, go, mo, st = orc.fine_propagate(po, inst.eps_iface, inst.eps_cell, inst.rho_in, None, 800)
+    assert np.array_equal(mg, mo)
+    assert 0 < mo.sum() < inst.nx
+    assert rel_err(rg, ro) < RHO64
+    assert rel_err(gg, go) < G64
+    m0 = np.sum(inst.rho_in)
+    assert abs(np.sum(ro) - m0) > 1e-13 * m0
+    assert abs((np.sum(rg) - m0) - (np.sum(ro) - m0)) < 1e-12 * m0
+
+
 def test_diagnostics_match_oracle(orc):
     inst = wl.small_hybrid(nx=80, nv=32, N=2, T=1e-3)
     p = sth.Problem(desc_of(inst, K=2))
@@ -217,6 +241,50 @@ def test_coarse_guess_matches_oracle(orc):
     for n in range(6):
         ref.append(orc.coarse_step(po, dtG, ref[-1]))
     assert rel_err(U, np.array(ref)) < 1e-13
+    p.close()
+
+
+@pytest.mark.parametrize("nx,field", [(100, True), (1500, True), (64, False)])
+def test_explicit_coarse_guess_matches_oracle(orc, nx, field):
+    """Coarse guess with G = S^0 (STH_COARSE_EXPLICIT): the step count per
+    interval and every slice value against the oracle's limit scheme
+    (nx = 1500 puts two cells on each thread with a ragged tail)."""
+    T = 0.02 if nx <= 100 else 2e-4
+    inst = wl.small_hybrid(nx=nx, nv=32, N=4, T=T)
+    inst.field_on = field
+    d = desc_of(inst)
+    d.flags |= sth.COARSE_EXPLICIT
+    p = sth.Problem(d)
+    po, ns, dtG = oracle_of(orc, inst)
+    po.flags |= orc.COARSE_EXPLICIT
+    assert p.info().coarse_steps == po.coarse_steps > 1
+    sth.sth_coarse_sweep(p)
+    U = sth.sth_get_rho(p)
+    ref = [inst.rho_in]
+    for n in range(inst.N):
+        ref.append(orc.coarse_step(po, dtG, ref[-1]))
+    assert rel_err(U, np.array(ref)) < 1e-12
+    m0 = np.sum(inst.rho_in)
+    assert np.max(np.abs(U.sum(axis=1) - m0)) < 1e-12 * m0
+    p.close()
+
+
+def test_explicit_coarse_parareal_matches_oracle(orc):
+    """Parareal iterations with the explicit coarse propagator: slice values
+    and successive errors against the oracle."""
+    inst = wl.small_hybrid(nx=96, nv=32, N=5, T=5e-3, K=3)
+    d = desc_of(inst, start_mode=sth.START_CARRY)
+    d.flags |= sth.COARSE_EXPLICIT
+    p = sth.Problem(d)
+    po, ns, dtG = oracle_of(orc, inst, start_mode=orc.START_CARRY)
+    po.flags |= orc.COARSE_EXPLICIT
+    errs = sth.parareal_solve(p, K=inst.K, fixed_iterations=True)
+    U = sth.sth_get_rho(p)
+    Uo, erro, it, kin = orc.parareal(po, inst.eps_iface, inst.eps_cell, inst.N, ns, dtG, inst.K, 0.0,
+                                     inst.rho_in)
+    assert rel_err(U, Uo) < 1e-11
+    assert np.allclose(errs, erro, rtol=1e-6, atol=1e-13)
+    assert p.info().kinetic_iface_steps == kin
     p.close()
 
 

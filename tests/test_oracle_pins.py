@@ -604,3 +604,87 @@ def test_hybrid_run_conserves_mass_and_switches(orc):
     assert abs(np.sum(rho) - m0) < 1e-13 * m0
     frac = st["kinetic_iface_steps"] / (3000 * inst.nx)
     assert 0.05 < frac < 0.99 and st["mask_flips"] > 0
+
+
+def test_literal_flux_differs_only_at_kinetic_fluid_boundaries(orc):
+    """Scheme S^HMM's cell-wise density update as printed (flag LITERAL_FLUX):
+    after one step it equals the flux-matched update in every cell except a
+    fluid cell next to a kinetic one (the only place where the two flux
+    choices differ), it equals it everywhere when all cells are fluid, and
+    it does not conserve mass in general while the flux-matched update does."""
+    inst = wl.small_hybrid(seed=2, nx=96, nv=32)
+    inst.rho_in = 1.0 + 0.3 * np.cos(2 * np.pi * wl.cell_centres(inst.nx))  # smooth: R small where eps is
+    flags = orc.FIELD | orc.HYBRID
+    po, ns, _ = orc.setup(inst.nx, inst.nv, inst.eps_iface, inst.rho_in, T=inst.T, N=inst.N,
+                          flags=flags, lift_order=1)
+    pl, _, _ = orc.setup(inst.nx, inst.nv, inst.eps_iface, inst.rho_in, T=inst.T, N=inst.N,
+                         flags=flags | orc.LITERAL_FLUX, lift_order=1)
+    g0 = np.zeros((inst.nx, inst.nv))  # the initial status comes from the criterion alone
+    mask0 = orc.diagnostics(po, inst.eps_iface, inst.eps_cell, inst.rho_in, g0)["mask"]
+    assert 0 < mask0.sum() < inst.nx  # both kinds of cells
+    rm, _, _, _ = orc.fine_propagate(po, inst.eps_iface, inst.eps_cell, inst.rho_in, g0, 1)
+    rl, _, _, _ = orc.fine_propagate(pl, inst.eps_iface, inst.eps_cell, inst.rho_in, g0, 1)
+    k = mask0.astype(bool)
+    boundary = (~k) & (np.roll(k, 1) | np.roll(k, -1))
+    assert np.array_equal(rm[~boundary], rl[~boundary])
+    assert np.any(rm[boundary] != rl[boundary])
+    # all fluid: identical
+    for q in (po, pl):
+        q.eta0 = q.delta0 = 1e300
+    rm, _, _, _ = orc.fine_propagate(po, inst.eps_iface, inst.eps_cell, inst.rho_in, g0, 20)
+    rl, _, _, _ = orc.fine_propagate(pl, inst.eps_iface, inst.eps_cell, inst.rho_in, g0, 20)
+    assert np.array_equal(rm, rl)
+    # mass: exact for flux matching, drifts for the cell-wise update
+    for q in (po, pl):
+        q.eta0 = q.delta0 = 1e-3
+    m0 = np.sum(inst.rho_in)
+    rm, _, _, _ = orc.fine_propagate(po, inst.eps_iface, inst.eps_cell, inst.rho_in, g0, 200)
+    rl, _, _, _ = orc.fine_propagate(pl, inst.eps_iface, inst.eps_cell, inst.rho_in, g0, 200)
+    assert abs(np.sum(rm) - m0) < 1e-13 * m0
+    assert abs(np.sum(rl) - m0) > 1e-13 * m0
+
+
+def test_explicit_coarse_is_the_limit_scheme(orc):
+    """COARSE_EXPLICIT: G is the explicit limit scheme S^0 in coarse_steps
+    steps.  Pinned by (a) the Fourier symbol of S^0 with the field off,
+    rho_hat -> (1 - 4 (m2 dt/dx^2) sin^2(pi k dx))^n rho_hat, and (b) the
+    all-fluid fine propagator with the same step, which is S^0 (bit for bit)."""
+    nx, nv, k, A = 64, 32, 3, 0.2
+    xc = wl.cell_centres(nx)
+    rho = 1.0 + A * np.cos(2 * np.pi * k * xc)
+    eps = np.full(nx, 1e-4)
+    p, ns, dtG = orc.setup(nx, nv, eps, rho, T=0.02, N=4, flags=orc.COARSE_EXPLICIT, lift_order=1)
+    assert p.coarse_steps > 1
+    out = orc.coarse_step(p, dtG, rho)
+    _, _, m2 = orc.velocity_grid(nv)
+    dx = 1.0 / nx
+    dt = dtG / p.coarse_steps
+    amp = A * (1.0 - 4.0 * m2 * dt / dx ** 2 * np.sin(np.pi * k * dx) ** 2) ** p.coarse_steps
+    assert np.max(np.abs(out - (1.0 + amp * np.cos(2 * np.pi * k * xc)))) < 1e-13
+    # with the field: the all-fluid fine propagator at the coarse step
+    rho2 = 1.0 + 0.3 * np.cos(2 * np.pi * xc) + 0.1 * np.sin(6 * np.pi * xc)
+    q, _, dtG2 = orc.setup(nx, nv, eps, rho2, T=0.02, N=4,
+                           flags=orc.FIELD | orc.COARSE_EXPLICIT, lift_order=1)
+    out2 = orc.coarse_step(q, dtG2, rho2)
+    f, _, _ = orc.setup(nx, nv, eps, rho2, T=0.02, N=4, flags=orc.FIELD | orc.HYBRID, lift_order=1)
+    f.dt = dtG2 / q.coarse_steps
+    f.eta0 = f.delta0 = 1e300  # every cell fluid: S^0
+    r2, _, _, _ = orc.fine_propagate(f, eps, eps, rho2, None, q.coarse_steps)
+    assert np.array_equal(out2, r2)
+    assert abs(np.sum(out2) - np.sum(rho2)) < 1e-13 * np.sum(rho2)
+
+
+def test_explicit_and_implicit_coarse_agree_to_first_order(orc):
+    """Both coarse propagators approximate the drift-diffusion limit: their
+    difference over one interval vanishes with the interval (at least
+    linearly; one step of each is a local error, second order here)."""
+    nx, nv = 64, 32
+    xc = wl.cell_centres(nx)
+    rho = 1.0 + 0.3 * np.cos(2 * np.pi * xc)
+    eps = np.full(nx, 1e-4)
+    diffs = []
+    for T in (4e-3, 2e-3, 1e-3):
+        pe, _, dtG = orc.setup(nx, nv, eps, rho, T=T, N=1, flags=orc.FIELD | orc.COARSE_EXPLICIT)
+        pi, _, _ = orc.setup(nx, nv, eps, rho, T=T, N=1, flags=orc.FIELD)
+        diffs.append(np.max(np.abs(orc.coarse_step(pe, dtG, rho) - orc.coarse_step(pi, dtG, rho))))
+    assert diffs[0] / diffs[1] > 1.9 and diffs[1] / diffs[2] > 1.9

@@ -132,7 +132,9 @@ int  sth_create(const sth_problem_desc *d, void *arena, size_t arena_bytes, sth_
 
 /* Coarse guess (first loop of Algorithm 1): U^n_0 = G(U^{n-1}_0) for
  * n = 1..N with G one backward-Euler drift-diffusion step of length T/N and
- * the field frozen at the slice start; caches G values for the correction. */
+ * the field frozen at the slice start (STH_COARSE_EXPLICIT: the explicit
+ * limit scheme S^0 of Section 3.3 over T/N); caches G values for the
+ * correction. */
 int  sth_coarse_sweep(sth_problem *p, void *stream);
 
 /* Fine propagator F = S^HMM (scheme of Section 2.3 with the cell rules of
@@ -147,6 +149,42 @@ int  sth_fine_sweep_batched(sth_problem *const *p, int count, void *stream);
  * synchronises and stores max_{n,i} |U^n_{k+1} - U^n_k|; k_out (optional)
  * receives the new k.  Returns STH_ESTATE if no fine sweep preceded it. */
 int  sth_parareal_correct(sth_problem *p, double *err_out, int *k_out, void *stream);
+
+/* The same correction for several problems in one launch (one workgroup per
+ * problem), each problem at its own k.  When errs_out is non-NULL the call
+ * synchronises once and stores each problem's error in errs_out[count].
+ * Every problem must have had a fine sweep since its last correction, and
+ * none may appear twice (STH_ESTATE / STH_EINVAL otherwise). */
+int  sth_parareal_correct_batched(sth_problem *const *p, int count, double *errs_out, void *stream);
+
+/* Successive errors err_0 .. err_{k-1} of the iterations done so far
+ * (Algorithm 1) to host_out[k].  Synchronises. */
+int  sth_get_errors(const sth_problem *p, double *host_out);
+
+/* A whole multiscale parareal solve of several problems recorded once as a
+ * HIP graph (stream capture) and replayed by one launch: the coarse guess,
+ * then for k = 0, 1, ... the fine sweep of every problem (all kernel classes
+ * concurrent, as sth_fine_sweep_batched) and their corrections in one
+ * launch (as sth_parareal_correct_batched).  Each problem stops on the
+ * device when err_k < tol or after min(k_max, N) iterations: its later
+ * kernels find its stop flag set and return at once, so no host round trip
+ * decides convergence.  A launch restarts every problem from U^0 = rho0
+ * (iteration count and kinetic counters cleared), so replays repeat the
+ * same solve.  The graph reads the problems' device memory and its own
+ * tables: the problems must outlive it and must not be used by other calls
+ * while a launch is in flight.  Recording runs no kernel; creation copies
+ * the tables to the device and synchronises. */
+typedef struct sth_graph sth_graph;
+int  sth_graph_create(sth_problem *const *p, int count, sth_graph **out);
+/* Enqueue one replay on `stream`.  The problems' host-side state is
+ * undefined until sth_graph_wait. */
+int  sth_graph_launch(sth_graph *g, void *stream);
+/* Synchronise `stream`, then settle each problem's state from the device:
+ * iterations done (iters_out[count], optional) and last error
+ * (last_err_out[count], optional).  Afterwards the problems continue with
+ * the ordinary calls. */
+int  sth_graph_wait(sth_graph *g, void *stream, int *iters_out, double *last_err_out);
+void sth_graph_destroy(sth_graph *g);
 
 /* Diagnostics of slice end n (0..N): the density U^n and, for n >= 1, the
  * perturbation the last fine sweep of slice n ended with (0 before any):

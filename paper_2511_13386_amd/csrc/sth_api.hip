@@ -42,8 +42,8 @@ size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Device layout of one problem (offsets from the arena base).
 struct Layout {
-    size_t cst, eps_p, eps_c, e_p, a_p, vtab, vrow64, vrow32, U, Gc, Fv, err, work, kin, mask, g0, gend, gst, units,
-        lifts, total;
+    size_t cst, eps_p, eps_c, e_p, a_p, vtab, vrow64, vrow32, U, Gc, Fv, err, errh, ctl, work, kin, mask, g0, gend,
+        gst, units, lifts, total;
 };
 
 Layout layout(int nx, int nv, int N, int realsz)
@@ -63,6 +63,8 @@ Layout layout(int nx, int nv, int N, int realsz)
     L.Gc = o;    o = al256(o + sizeof(double) * (size_t)(N + 1) * nx);
     L.Fv = o;    o = al256(o + sizeof(double) * (size_t)(N + 1) * nx);
     L.err = o;   o = al256(o + sizeof(double) * 4);
+    L.errh = o;  o = al256(o + sizeof(double) * (size_t)(N + 1));
+    L.ctl = o;   o = al256(o + sizeof(int) * 4);
     L.work = o;  o = al256(o + sizeof(double) * 9 * (size_t)nx);
     L.kin = o;   o = al256(o + sizeof(unsigned long long) * (size_t)(N + 1));
     L.mask = o;  o = al256(o + sizeof(int) * (size_t)nx);
@@ -182,6 +184,18 @@ struct sth_problem {
     size_t gslab() const { return fine_slot_elems(nx, nv) * realsz; }
 };
 
+// A recorded whole solve of several problems (see sth_graph_create).
+struct sth_graph {
+    std::vector<sth_problem *> probs;
+    std::vector<int> kmax;        // iterations of each problem at most
+    int iters = 0;                // iterations recorded
+    char *dbuf = nullptr;         // device tables the graph reads
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cap = nullptr;    // capture stream
+    bool launched = false;
+};
+
 namespace {
 
 // Host set-up: velocity grid, discretely normalised Maxwellian, m2.
@@ -286,6 +300,138 @@ FineUnit make_unit(const sth_problem *p, int n)
     u.mask_out = nullptr;
     u.nsteps = p->ns;
     return u;
+}
+
+// One fine unit of a batched sweep with its kernel class and cost.
+struct SweepItem {
+    FineShape shape;
+    FineUnit unit;
+    double cost;
+};
+
+// Units of iteration k of one problem (slices n = k+1..N), with the jobs
+// that prepare their start perturbations: the given g0 for slice 1, a copy
+// of the previous slice's end state (carry mode, when one exists), else the
+// lifting of the slice-start density.  `have_end` says which slices have an
+// end state; `stop` goes into every unit and job.
+void plan_problem_sweep(sth_problem *p, int k, const std::vector<char> &have_end, const int *stop,
+                        std::vector<SweepItem> &items, std::vector<LiftJob> &lifts, std::vector<CopyJob> &copies)
+{
+    const FineShape sh = fine_shape(p->prec, p->nx, p->nv, 0, 0);
+    for (int n = k + 1; n <= p->N; ++n) {
+        FineUnit u = make_unit(p, n);
+        u.stop = stop;
+        void *gst = p->base + p->L.gst + (size_t)n * p->gslab();
+        if (n == 1) {
+            u.g_in = p->has_g0 ? (const void *)(p->base + p->L.g0) : nullptr;
+        } else if (p->start_mode == STH_START_CARRY && have_end[n - 1]) {
+            CopyJob c{};
+            c.src = (const uint4 *)(p->base + p->L.gend + (size_t)(n - 1) * p->gslab());
+            c.dst = (uint4 *)gst;
+            c.n = p->gslab() / sizeof(uint4);
+            c.stop = stop;
+            copies.push_back(c);
+            u.g_in = gst;
+        } else {
+            LiftJob lj{};
+            lj.pc = p->at<FineConst>(p->L.cst);
+            lj.rho = p->at<double>(p->L.U) + (size_t)(n - 1) * p->nx;
+            lj.g = gst;
+            lj.lift_order = p->lift_order;
+            lj.stop = stop;
+            lifts.push_back(lj);
+            u.g_in = gst;
+        }
+        items.push_back({sh, u, (double)p->ns * p->nx * p->nv});
+    }
+}
+
+bool same_class(const FineShape &a, const FineShape &b)
+{
+    return a.prec == b.prec && a.nv == b.nv && a.stream == b.stream && a.ipt == b.ipt && a.block == b.block;
+}
+
+// Group by kernel class, longest units first within a class (LPT order of
+// dispatch).
+void sort_items(std::vector<SweepItem> &items)
+{
+    std::stable_sort(items.begin(), items.end(), [](const SweepItem &a, const SweepItem &b) {
+        if (a.shape.prec != b.shape.prec) return a.shape.prec < b.shape.prec;
+        if (a.shape.nv != b.shape.nv) return a.shape.nv < b.shape.nv;
+        if (a.shape.stream != b.shape.stream) return a.shape.stream < b.shape.stream;
+        if (a.shape.ipt != b.shape.ipt) return a.shape.ipt < b.shape.ipt;
+        if (a.shape.block != b.shape.block) return a.shape.block < b.shape.block;
+        return a.cost > b.cost;
+    });
+}
+
+// Launch the sorted units (device table dtab, same order): one launch per
+// kernel class; with several classes the costliest runs on st and the others
+// on the side streams, all concurrent, joined back into st.
+int issue_classes(const std::vector<SweepItem> &items, FineUnit *dtab, hipStream_t st)
+{
+    struct Group {
+        FineShape sh;
+        size_t begin, end;
+        double cost;
+    };
+    std::vector<Group> groups;
+    size_t begin = 0;
+    while (begin < items.size()) {
+        size_t end = begin + 1;
+        FineShape sh = items[begin].shape;
+        size_t lds = sh.lds;
+        double cost = items[begin].cost;
+        while (end < items.size() && same_class(items[end].shape, sh)) {
+            lds = std::max(lds, items[end].shape.lds);
+            cost += items[end].cost;
+            ++end;
+        }
+        sh.lds = lds;
+        groups.push_back({sh, begin, end, cost});
+        begin = end;
+    }
+    if (groups.empty()) return STH_OK;
+    if (groups.size() == 1) {
+        HIPCHK(launch_fine(groups[0].sh, dtab, (int)items.size(), st));
+        return STH_OK;
+    }
+    std::stable_sort(groups.begin(), groups.end(), [](const Group &a, const Group &b) { return a.cost > b.cost; });
+    SidePool *P = nullptr;
+    int rc = side_pool(&P);
+    if (rc) return rc;
+    // the fork/join events are shared: issue one batch at a time
+    std::lock_guard<std::mutex> lk(g_side_issue_mu);
+    const int nside = std::min<int>(kSideStreams, (int)groups.size() - 1);
+    HIPCHK(hipEventRecord(P->fork, st));
+    for (int i = 0; i < nside; ++i) HIPCHK(hipStreamWaitEvent(P->s[i], P->fork, 0));
+    for (size_t g = 0; g < groups.size(); ++g) {
+        const int lane = (int)(g % (size_t)(nside + 1));
+        hipStream_t gs = lane == 0 ? st : P->s[lane - 1];
+        HIPCHK(launch_fine(groups[g].sh, dtab + groups[g].begin, (int)(groups[g].end - groups[g].begin), gs));
+    }
+    for (int i = 0; i < nside; ++i) {
+        HIPCHK(hipEventRecord(P->join[i], P->s[i]));
+        HIPCHK(hipStreamWaitEvent(st, P->join[i], 0));
+    }
+    return STH_OK;
+}
+
+CoarseJob coarse_job_of(sth_problem *p, int mode, int k)
+{
+    CoarseJob j{};
+    j.pc = p->at<FineConst>(p->L.cst);
+    j.U = p->at<double>(p->L.U);
+    j.Gc = p->at<double>(p->L.Gc);
+    j.Fv = p->at<double>(p->L.Fv);
+    j.err = p->at<double>(p->L.err);
+    j.work = p->at<double>(p->L.work);
+    j.dtG = p->dtG;
+    j.N = p->N;
+    j.mode = mode;
+    j.k = k;
+    j.errh = p->at<double>(p->L.errh);
+    return j;
 }
 
 }  // namespace
@@ -436,17 +582,7 @@ void sth_destroy(sth_problem *p)
 int sth_coarse_sweep(sth_problem *p, void *stream)
 {
     if (!p) return fail(STH_EINVAL, "null problem");
-    CoarseJob j{};
-    j.pc = p->at<FineConst>(p->L.cst);
-    j.U = p->at<double>(p->L.U);
-    j.Gc = p->at<double>(p->L.Gc);
-    j.Fv = p->at<double>(p->L.Fv);
-    j.err = p->at<double>(p->L.err);
-    j.work = p->at<double>(p->L.work);
-    j.dtG = p->dtG;
-    j.N = p->N;
-    j.mode = 0;
-    j.k = 0;
+    const CoarseJob j = coarse_job_of(p, 0, 0);
     HIPCHK(launch_coarse(j, p->nx, (p->flags & STH_COARSE_EXPLICIT) != 0, (hipStream_t)stream));
     p->coarse_done = true;
     p->k = 0;
@@ -459,55 +595,26 @@ int sth_fine_sweep_batched(sth_problem *const *probs, int count, void *stream)
 {
     if (count < 0 || (count > 0 && !probs)) return fail(STH_EINVAL, "bad batch");
     hipStream_t st = (hipStream_t)stream;
-    struct Item {
-        FineShape shape;
-        FineUnit unit;
-        double cost;
-    };
-    std::vector<Item> items;
+    for (int b = 0; b < count; ++b) {
+        if (!probs[b]) return fail(STH_EINVAL, "null problem in batch");
+        if (!probs[b]->coarse_done) return fail(STH_ESTATE, "sth_coarse_sweep must precede the fine sweep");
+    }
+    std::vector<SweepItem> items;
     for (int b = 0; b < count; ++b) {
         sth_problem *p = probs[b];
-        if (!p) return fail(STH_EINVAL, "null problem in batch");
-        if (!p->coarse_done) return fail(STH_ESTATE, "sth_coarse_sweep must precede the fine sweep");
         if (p->k >= p->N) continue;
-        const FineShape sh = fine_shape(p->prec, p->nx, p->nv, 0, 0);
-        // slice-start perturbations
         std::vector<LiftJob> lifts;
-        for (int n = p->k + 1; n <= p->N; ++n) {
-            FineUnit u = make_unit(p, n);
-            void *gst = p->base + p->L.gst + (size_t)n * p->gslab();
-            if (n == 1) {
-                u.g_in = p->has_g0 ? (const void *)(p->base + p->L.g0) : nullptr;
-            } else if (p->start_mode == STH_START_CARRY && p->have_end[n - 1]) {
-                HIPCHK(hipMemcpyAsync(gst, p->base + p->L.gend + (size_t)(n - 1) * p->gslab(),
-                                      p->gslab(), hipMemcpyDeviceToDevice, st));
-                u.g_in = gst;
-            } else {
-                LiftJob lj{};
-                lj.pc = p->at<FineConst>(p->L.cst);
-                lj.rho = p->at<double>(p->L.U) + (size_t)(n - 1) * p->nx;
-                lj.g = gst;
-                lj.lift_order = p->lift_order;
-                lifts.push_back(lj);
-                u.g_in = gst;
-            }
-            items.push_back({sh, u, (double)p->ns * p->nx * p->nv});
-        }
+        std::vector<CopyJob> copies;
+        plan_problem_sweep(p, p->k, p->have_end, nullptr, items, lifts, copies);
+        for (const CopyJob &c : copies)
+            HIPCHK(hipMemcpyAsync(c.dst, c.src, c.n * sizeof(uint4), hipMemcpyDeviceToDevice, st));
         if (!lifts.empty()) {
             LiftJob *dl = p->at<LiftJob>(p->L.lifts);
             HIPCHK(hipMemcpyAsync(dl, lifts.data(), sizeof(LiftJob) * lifts.size(), hipMemcpyHostToDevice, st));
             HIPCHK(launch_lift(p->prec, dl, (int)lifts.size(), p->nx, st));
         }
     }
-    // group by kernel class, longest units first (LPT order of dispatch)
-    std::stable_sort(items.begin(), items.end(), [](const Item &a, const Item &b) {
-        if (a.shape.prec != b.shape.prec) return a.shape.prec < b.shape.prec;
-        if (a.shape.nv != b.shape.nv) return a.shape.nv < b.shape.nv;
-        if (a.shape.stream != b.shape.stream) return a.shape.stream < b.shape.stream;
-        if (a.shape.ipt != b.shape.ipt) return a.shape.ipt < b.shape.ipt;
-        if (a.shape.block != b.shape.block) return a.shape.block < b.shape.block;
-        return a.cost > b.cost;
-    });
+    sort_items(items);
     if (!items.empty()) {
         int slot = 0;
         int rc = acquire_table(sizeof(FineUnit) * items.size(), &slot);
@@ -516,55 +623,8 @@ int sth_fine_sweep_batched(sth_problem *const *probs, int count, void *stream)
         std::vector<FineUnit> host(items.size());
         for (size_t t = 0; t < items.size(); ++t) host[t] = items[t].unit;
         HIPCHK(hipMemcpyAsync(dtab, host.data(), sizeof(FineUnit) * host.size(), hipMemcpyHostToDevice, st));
-        // kernel classes: runs of equal shape in the sorted table
-        struct Group {
-            FineShape sh;
-            size_t begin, end;
-            double cost;
-        };
-        std::vector<Group> groups;
-        size_t begin = 0;
-        while (begin < items.size()) {
-            size_t end = begin + 1;
-            FineShape sh = items[begin].shape;
-            size_t lds = sh.lds;
-            double cost = items[begin].cost;
-            while (end < items.size() && items[end].shape.prec == sh.prec && items[end].shape.nv == sh.nv &&
-                   items[end].shape.stream == sh.stream && items[end].shape.ipt == sh.ipt &&
-                   items[end].shape.block == sh.block) {
-                lds = std::max(lds, items[end].shape.lds);
-                cost += items[end].cost;
-                ++end;
-            }
-            sh.lds = lds;
-            groups.push_back({sh, begin, end, cost});
-            begin = end;
-        }
-        if (groups.size() == 1) {
-            HIPCHK(launch_fine(groups[0].sh, dtab, (int)items.size(), st));
-        } else {
-            // several classes: the costliest on the caller's stream, the others
-            // spread over the side streams, all concurrent
-            std::stable_sort(groups.begin(), groups.end(),
-                             [](const Group &a, const Group &b) { return a.cost > b.cost; });
-            SidePool *P = nullptr;
-            int rc2 = side_pool(&P);
-            if (rc2) return rc2;
-            // the fork/join events are shared: issue one batch at a time
-            std::lock_guard<std::mutex> lk(g_side_issue_mu);
-            const int nside = std::min<int>(kSideStreams, (int)groups.size() - 1);
-            HIPCHK(hipEventRecord(P->fork, st));
-            for (int i = 0; i < nside; ++i) HIPCHK(hipStreamWaitEvent(P->s[i], P->fork, 0));
-            for (size_t g = 0; g < groups.size(); ++g) {
-                const int lane = (int)(g % (size_t)(nside + 1));
-                hipStream_t gs = lane == 0 ? st : P->s[lane - 1];
-                HIPCHK(launch_fine(groups[g].sh, dtab + groups[g].begin, (int)(groups[g].end - groups[g].begin), gs));
-            }
-            for (int i = 0; i < nside; ++i) {
-                HIPCHK(hipEventRecord(P->join[i], P->s[i]));
-                HIPCHK(hipStreamWaitEvent(st, P->join[i], 0));
-            }
-        }
+        rc = issue_classes(items, dtab, st);
+        if (rc) return rc;
         HIPCHK(hipEventRecord(g_pool[slot].ev, st));
         g_pool[slot].used = true;
     }
@@ -582,17 +642,7 @@ int sth_parareal_correct(sth_problem *p, double *err_out, int *k_out, void *stre
     if (!p->swept) return fail(STH_ESTATE, "sth_fine_sweep_batched must precede the correction");
     if (p->k >= p->N) return fail(STH_ESTATE, "all slices converged");
     hipStream_t st = (hipStream_t)stream;
-    CoarseJob j{};
-    j.pc = p->at<FineConst>(p->L.cst);
-    j.U = p->at<double>(p->L.U);
-    j.Gc = p->at<double>(p->L.Gc);
-    j.Fv = p->at<double>(p->L.Fv);
-    j.err = p->at<double>(p->L.err);
-    j.work = p->at<double>(p->L.work);
-    j.dtG = p->dtG;
-    j.N = p->N;
-    j.mode = 1;
-    j.k = p->k;
+    const CoarseJob j = coarse_job_of(p, 1, p->k);
     HIPCHK(launch_coarse(j, p->nx, (p->flags & STH_COARSE_EXPLICIT) != 0, st));
     p->k += 1;
     p->swept = false;
@@ -606,6 +656,273 @@ int sth_parareal_correct(sth_problem *p, double *err_out, int *k_out, void *stre
     if (k_out) *k_out = p->k;
     return STH_OK;
 }
+
+int sth_parareal_correct_batched(sth_problem *const *probs, int count, double *errs_out, void *stream)
+{
+    if (count < 0 || (count > 0 && !probs)) return fail(STH_EINVAL, "bad batch");
+    for (int b = 0; b < count; ++b) {
+        sth_problem *p = probs[b];
+        if (!p) return fail(STH_EINVAL, "null problem in batch");
+        if (!p->swept) return fail(STH_ESTATE, "sth_fine_sweep_batched must precede the correction");
+        if (p->k >= p->N) return fail(STH_ESTATE, "all slices converged");
+        for (int c = 0; c < b; ++c)
+            if (probs[c] == p) return fail(STH_EINVAL, "a problem appears twice in the batch");
+    }
+    if (count == 0) return STH_OK;
+    hipStream_t st = (hipStream_t)stream;
+    // table: the jobs, then one error slot per job (one read-back for all)
+    const size_t jbytes = al256(sizeof(CoarseJob) * (size_t)count);
+    int slot = 0;
+    int rc = acquire_table(jbytes + sizeof(double) * (size_t)count, &slot);
+    if (rc) return rc;
+    char *tab = (char *)g_pool[slot].ptr;
+    double *derr = (double *)(tab + jbytes);
+    std::vector<CoarseJob> jobs(count);
+    int block = kWave;
+    size_t lds = 0;
+    for (int b = 0; b < count; ++b) {
+        sth_problem *p = probs[b];
+        jobs[b] = coarse_job_of(p, 1, p->k);
+        jobs[b].err = derr + b;
+        int bb = 0;
+        size_t ll = 0;
+        coarse_launch_dims(p->nx, (p->flags & STH_COARSE_EXPLICIT) != 0, &bb, &ll);
+        block = std::max(block, bb);
+        lds = std::max(lds, ll);
+    }
+    HIPCHK(hipMemcpyAsync(tab, jobs.data(), sizeof(CoarseJob) * jobs.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(launch_coarse_many((const CoarseJob *)tab, count, block, lds, st));
+    std::vector<double> errs(count, 0.0);
+    if (errs_out) HIPCHK(hipMemcpyAsync(errs.data(), derr, sizeof(double) * count, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipEventRecord(g_pool[slot].ev, st));
+    g_pool[slot].used = true;
+    if (errs_out) HIPCHK(hipStreamSynchronize(st));
+    for (int b = 0; b < count; ++b) {
+        sth_problem *p = probs[b];
+        p->k += 1;
+        p->swept = false;
+        if (errs_out) {
+            errs_out[b] = errs[b];
+            p->last_err = errs[b];
+        }
+    }
+    return STH_OK;
+}
+
+namespace {
+
+// Operations of a recorded solve, in issue order; offsets into the graph's
+// device table buffer.
+struct GraphOp {
+    enum Kind { COARSE, LIFT, COPY, FINE } kind;
+    size_t off;
+    int n;              // jobs or units
+    int a;              // COARSE: block; LIFT: precision
+    size_t b;           // COARSE: LDS bytes; LIFT: nx; COPY: largest job (16-byte words)
+    size_t items_begin; // FINE: range in the graph's item list
+    size_t items_end;
+};
+
+struct TableBuilder {
+    std::vector<char> host;
+    size_t put(const void *src, size_t bytes)
+    {
+        const size_t off = al256(host.size());
+        host.resize(off + bytes);
+        if (bytes) std::memcpy(host.data() + off, src, bytes);
+        return off;
+    }
+};
+
+void destroy_graph(sth_graph *g)
+{
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->cap) (void)hipStreamDestroy(g->cap);
+    if (g->dbuf) (void)hipFree(g->dbuf);
+    delete g;
+}
+
+}  // namespace
+
+int sth_graph_create(sth_problem *const *probs, int count, sth_graph **out)
+{
+    if (!out) return fail(STH_EINVAL, "null output");
+    *out = nullptr;
+    if (count <= 0 || !probs) return fail(STH_EINVAL, "bad batch");
+    for (int b = 0; b < count; ++b) {
+        if (!probs[b]) return fail(STH_EINVAL, "null problem in batch");
+        for (int c = 0; c < b; ++c)
+            if (probs[c] == probs[b]) return fail(STH_EINVAL, "a problem appears twice in the batch");
+    }
+    sth_graph *g = new sth_graph();
+    g->probs.assign(probs, probs + count);
+    for (sth_problem *p : g->probs) {
+        const int km = std::max(0, std::min(p->K, p->N));
+        g->kmax.push_back(km);
+        g->iters = std::max(g->iters, km);
+    }
+    // plan every launch of the solve on the host
+    TableBuilder tb;
+    std::vector<GraphOp> ops;
+    std::vector<SweepItem> all_items;
+    auto coarse_op = [&](int mode, int k) {
+        std::vector<CoarseJob> jobs;
+        int block = kWave;
+        size_t lds = 0;
+        for (size_t b = 0; b < g->probs.size(); ++b) {
+            sth_problem *p = g->probs[b];
+            if (mode == 1 && k >= g->kmax[b]) continue;
+            CoarseJob j = coarse_job_of(p, mode, k);
+            j.ctl = p->at<int>(p->L.ctl);
+            j.kin = p->at<unsigned long long>(p->L.kin);
+            j.tol = p->tol;
+            j.kmax = g->kmax[b];
+            jobs.push_back(j);
+            int bb = 0;
+            size_t ll = 0;
+            coarse_launch_dims(p->nx, (p->flags & STH_COARSE_EXPLICIT) != 0, &bb, &ll);
+            block = std::max(block, bb);
+            lds = std::max(lds, ll);
+        }
+        if (jobs.empty()) return;
+        GraphOp op{GraphOp::COARSE, tb.put(jobs.data(), sizeof(CoarseJob) * jobs.size()), (int)jobs.size(), block,
+                   lds, 0, 0};
+        ops.push_back(op);
+    };
+    coarse_op(0, 0);
+    std::vector<std::vector<char>> have(g->probs.size());
+    for (size_t b = 0; b < g->probs.size(); ++b) have[b].assign(g->probs[b]->N + 1, 0);
+    for (int k = 0; k < g->iters; ++k) {
+        std::vector<SweepItem> items;
+        std::vector<CopyJob> copies;
+        size_t max_copy = 0;
+        for (size_t b = 0; b < g->probs.size(); ++b) {
+            sth_problem *p = g->probs[b];
+            if (k >= g->kmax[b]) continue;
+            const int *stop = p->at<int>(p->L.ctl) + 1;
+            std::vector<LiftJob> lifts;
+            plan_problem_sweep(p, k, have[b], stop, items, lifts, copies);
+            if (!lifts.empty()) {
+                GraphOp op{GraphOp::LIFT, tb.put(lifts.data(), sizeof(LiftJob) * lifts.size()), (int)lifts.size(),
+                           p->prec, (size_t)p->nx, 0, 0};
+                ops.push_back(op);
+            }
+            for (int n = k + 1; n <= p->N; ++n) have[b][n] = 1;
+        }
+        for (const CopyJob &c : copies) max_copy = std::max(max_copy, c.n);
+        for (size_t c0 = 0; c0 < copies.size(); c0 += 65535) {
+            const size_t nc = std::min<size_t>(65535, copies.size() - c0);
+            GraphOp op{GraphOp::COPY, tb.put(copies.data() + c0, sizeof(CopyJob) * nc), (int)nc, 0, max_copy, 0, 0};
+            ops.push_back(op);
+        }
+        sort_items(items);
+        std::vector<FineUnit> units(items.size());
+        for (size_t t = 0; t < items.size(); ++t) units[t] = items[t].unit;
+        GraphOp op{GraphOp::FINE, tb.put(units.data(), sizeof(FineUnit) * units.size()), (int)units.size(), 0, 0,
+                   all_items.size(), all_items.size() + items.size()};
+        ops.push_back(op);
+        all_items.insert(all_items.end(), items.begin(), items.end());
+        coarse_op(1, k);
+    }
+    // upload the tables, then record the launches
+    hipError_t e = hipMalloc(&g->dbuf, std::max<size_t>(tb.host.size(), 256));
+    if (e == hipSuccess) e = hipMemcpy(g->dbuf, tb.host.data(), tb.host.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        destroy_graph(g);
+        return hip_fail(e, "sth_graph_create: set-up");
+    }
+    e = hipStreamBeginCapture(g->cap, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) {
+        destroy_graph(g);
+        return hip_fail(e, "hipStreamBeginCapture");
+    }
+    int rc = STH_OK;
+    for (const GraphOp &op : ops) {
+        void *tab = g->dbuf + op.off;
+        hipError_t le = hipSuccess;
+        switch (op.kind) {
+            case GraphOp::COARSE: le = launch_coarse_many((const CoarseJob *)tab, op.n, op.a, op.b, g->cap); break;
+            case GraphOp::LIFT: le = launch_lift(op.a, (const LiftJob *)tab, op.n, (int)op.b, g->cap); break;
+            case GraphOp::COPY: le = launch_copy((const CopyJob *)tab, op.n, op.b, g->cap); break;
+            case GraphOp::FINE: {
+                std::vector<SweepItem> items(all_items.begin() + op.items_begin, all_items.begin() + op.items_end);
+                rc = issue_classes(items, (FineUnit *)tab, g->cap);
+                break;
+            }
+        }
+        if (le != hipSuccess) rc = hip_fail(le, "sth_graph_create: recording a launch");
+        if (rc) break;
+    }
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(g->cap, &graph);
+    g->graph = graph;
+    if (rc) {
+        destroy_graph(g);
+        return rc;
+    }
+    if (e != hipSuccess) {
+        destroy_graph(g);
+        return hip_fail(e, "hipStreamEndCapture");
+    }
+    e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        destroy_graph(g);
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    *out = g;
+    return STH_OK;
+}
+
+int sth_graph_launch(sth_graph *g, void *stream)
+{
+    if (!g || !g->exec) return fail(STH_EINVAL, "null graph");
+    HIPCHK(hipGraphLaunch(g->exec, (hipStream_t)stream));
+    g->launched = true;
+    for (sth_problem *p : g->probs) {
+        // host bookkeeping is settled by sth_graph_wait
+        p->coarse_done = false;
+        p->swept = false;
+    }
+    return STH_OK;
+}
+
+int sth_graph_wait(sth_graph *g, void *stream, int *iters_out, double *last_err_out)
+{
+    if (!g) return fail(STH_EINVAL, "null graph");
+    if (!g->launched) return fail(STH_ESTATE, "the graph has not been launched");
+    HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+    for (size_t b = 0; b < g->probs.size(); ++b) {
+        sth_problem *p = g->probs[b];
+        int ctl[2] = {0, 0};
+        HIPCHK(hipMemcpy(ctl, p->at<int>(p->L.ctl), sizeof(ctl), hipMemcpyDeviceToHost));
+        const int k = std::max(0, std::min(ctl[0], p->N));
+        double e = -1.0;
+        if (k > 0) HIPCHK(hipMemcpy(&e, p->at<double>(p->L.errh) + (k - 1), sizeof(double), hipMemcpyDeviceToHost));
+        p->k = k;
+        p->last_err = e;
+        p->coarse_done = true;
+        p->swept = false;
+        std::fill(p->have_end.begin(), p->have_end.end(), 0);
+        if (k > 0)
+            for (int n = 1; n <= p->N; ++n) p->have_end[n] = 1;
+        if (iters_out) iters_out[b] = k;
+        if (last_err_out) last_err_out[b] = e;
+    }
+    return STH_OK;
+}
+
+int sth_get_errors(const sth_problem *p, double *host_out)
+{
+    if (!p || !host_out) return fail(STH_EINVAL, "null argument");
+    HIPCHK(hipDeviceSynchronize());
+    if (p->k > 0) HIPCHK(hipMemcpy(host_out, p->at<double>(p->L.errh), sizeof(double) * p->k, hipMemcpyDeviceToHost));
+    return STH_OK;
+}
+
+void sth_graph_destroy(sth_graph *g) { destroy_graph(g); }
 
 int sth_moments_criteria(const sth_problem *p, int slice, double *E, double *J, double *Phi, double *N,
                          double *R, int *cell_mask, void *stream)

@@ -55,6 +55,8 @@ struct FineUnit {
     unsigned long long *kin;  // kinetic interface-steps counter (atomic add)
     int *mask_out;            // [nx] final cell status, or NULL
     long long nsteps;         // steps of this unit (<= 0: pc->nsteps)
+    const int *stop;          // the problem's stop flag (the unit does nothing
+                              // when it is set), or NULL
 };
 
 // Launch shape of a fine-sweep kernel class.
@@ -77,6 +79,7 @@ struct LiftJob {
     const double *rho;    // [nx]
     void *g;              // [nv][ld] v-major Real
     int lift_order;
+    const int *stop;      // skip when set, or NULL
 };
 hipError_t launch_lift(int prec, const LiftJob *d_jobs, int njobs, int nx, hipStream_t st);
 
@@ -93,8 +96,33 @@ struct CoarseJob {
     int N;
     int mode;             // 0 = coarse guess, 1 = correction
     int k;                // iteration index (correction)
+    // Device-side iteration control, or NULL.  ctl[0] = iterations done,
+    // ctl[1] = stop flag.  Mode 0 clears both and the kinetic counters
+    // kin[0..N]; mode 1 does nothing when the stop flag is set, else it
+    // corrects, stores ctl[0] = k + 1 and sets the flag when
+    // err < tol or k + 1 >= kmax.
+    int *ctl;
+    double *errh;         // [N] error of each iteration (mode 1), or NULL
+    unsigned long long *kin;
+    double tol;
+    int kmax;
+    int pad;
 };
+// One problem (one workgroup, job by value).
 hipError_t launch_coarse(const CoarseJob &job, int nx, bool explicit_scheme, hipStream_t st);
+// Several problems in one launch, one workgroup each: block threads and
+// dynamic LDS bytes cover the largest job (coarse_launch_dims).
+void coarse_launch_dims(int nx, bool explicit_scheme, int *block, size_t *lds);
+hipError_t launch_coarse_many(const CoarseJob *d_jobs, int njobs, int block, size_t lds, hipStream_t st);
+
+// Device-to-device copy of n 16-byte words, skipped when *stop is set.
+struct CopyJob {
+    const uint4 *src;
+    uint4 *dst;
+    size_t n;
+    const int *stop;
+};
+hipError_t launch_copy(const CopyJob *d_jobs, int njobs, size_t max_n, hipStream_t st);
 
 // Diagnostics of a state (rho, g).
 struct DiagJob {

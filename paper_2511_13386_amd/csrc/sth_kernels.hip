@@ -528,6 +528,7 @@ __global__ void __launch_bounds__(kFineBlock) k_fine(const FineUnit *__restrict_
     extern __shared__ __align__(16) unsigned char smem[];
 
     const FineUnit &U = units[blockIdx.x];
+    if (U.stop && *U.stop) return;  // the problem has converged: uniform exit
     const FineConst *__restrict__ C = &U.c;
     const int nx = C->nx;
     const int ld = fine_ld(nx);
@@ -1165,6 +1166,7 @@ __global__ void __launch_bounds__(1024) k_lift(const LiftJob *__restrict__ jobs)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const LiftJob J = jobs[blockIdx.x];
+    if (J.stop && *J.stop) return;
     const FineConst *C = J.pc;
     const int nx = C->nx, nv = C->nv;
     const bool field = C->flags & STH_FIELD;
@@ -1359,13 +1361,22 @@ __device__ void coarse_any_block(const FineConst *C, const double *rin, double *
     else coarse_step_block(C, rin, rout, dtG, w);
 }
 
-__global__ void __launch_bounds__(1024) k_coarse(CoarseJob J)
+// Coarse guess (mode 0) or parareal correction (mode 1) of one problem by
+// one workgroup, sequential over the slices (Algorithm 1).
+__device__ void coarse_job(const CoarseJob &J)
 {
     double *work = J.work;
     const int nx = J.pc->nx;
     const size_t slab = (size_t)nx;
     double *gn = work + 8 * slab;
     if (J.mode == 0) {
+        if (J.ctl) {
+            if (threadIdx.x == 0) {
+                J.ctl[0] = 0;
+                J.ctl[1] = 0;
+            }
+            for (int n = threadIdx.x; n <= J.N; n += blockDim.x) J.kin[n] = 0ull;
+        }
         for (int n = 1; n <= J.N; ++n) {
             coarse_any_block(J.pc, J.U + (n - 1) * slab, J.U + n * slab, J.dtG, work);
             for (int i = threadIdx.x; i < nx; i += blockDim.x) J.Gc[n * slab + i] = J.U[n * slab + i];
@@ -1373,6 +1384,7 @@ __global__ void __launch_bounds__(1024) k_coarse(CoarseJob J)
         }
         return;
     }
+    if (J.ctl && J.ctl[1]) return;  // converged: uniform exit
     const int k = J.k;
     double e = 0.0;
     for (int i = threadIdx.x; i < nx; i += blockDim.x) {
@@ -1395,20 +1407,75 @@ __global__ void __launch_bounds__(1024) k_coarse(CoarseJob J)
         __syncthreads();
     }
     e = block_max(e);
-    if (threadIdx.x == 0) J.err[0] = e;
+    if (threadIdx.x == 0) {
+        J.err[0] = e;
+        if (J.errh) J.errh[k] = e;
+        if (J.ctl) {
+            J.ctl[0] = k + 1;
+            J.ctl[1] = (e < J.tol || k + 1 >= J.kmax) ? 1 : 0;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(1024) k_coarse(CoarseJob J) { coarse_job(J); }
+
+__global__ void __launch_bounds__(1024) k_coarse_many(const CoarseJob *__restrict__ jobs)
+{
+    const CoarseJob J = jobs[blockIdx.x];
+    coarse_job(J);
+}
+
+void coarse_launch_dims(int nx, bool explicit_scheme, int *block, size_t *lds)
+{
+    int b = ((nx + kWave - 1) / kWave) * kWave;
+    if (b > 1024) b = 1024;
+    *block = b;
+    *lds = explicit_scheme ? sizeof(double) * (2 * (size_t)nx + 32) : 0;
 }
 
 hipError_t launch_coarse(const CoarseJob &job, int nx, bool explicit_scheme, hipStream_t st)
 {
-    int b = ((nx + kWave - 1) / kWave) * kWave;
-    if (b > 1024) b = 1024;
-    const size_t lds = explicit_scheme ? sizeof(double) * (2 * (size_t)nx + 32) : 0;
+    int b = 0;
+    size_t lds = 0;
+    coarse_launch_dims(nx, explicit_scheme, &b, &lds);
     if (lds) {
         hipError_t e = hipFuncSetAttribute((const void *)k_coarse, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)lds);
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_coarse, dim3(1), dim3(b), lds, st, job);
+    return hipGetLastError();
+}
+
+hipError_t launch_coarse_many(const CoarseJob *d_jobs, int njobs, int block, size_t lds, hipStream_t st)
+{
+    if (njobs <= 0) return hipSuccess;
+    if (block <= 0 || block > 1024 || block % kWave) return hipErrorInvalidValue;
+    if (lds) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_coarse_many,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_coarse_many, dim3(njobs), dim3(block), lds, st, d_jobs);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ copies
+__global__ void __launch_bounds__(256) k_copy(const CopyJob *__restrict__ jobs)
+{
+    const CopyJob J = jobs[blockIdx.y];
+    if (J.stop && *J.stop) return;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < J.n; i += (size_t)gridDim.x * 256)
+        J.dst[i] = J.src[i];
+}
+
+hipError_t launch_copy(const CopyJob *d_jobs, int njobs, size_t max_n, hipStream_t st)
+{
+    if (njobs <= 0 || max_n == 0) return hipSuccess;
+    if (njobs > 65535) return hipErrorInvalidValue;
+    size_t gx = (max_n + 255) / 256;
+    if (gx > 256) gx = 256;
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)gx, (unsigned)njobs), dim3(256), 0, st, d_jobs);
     return hipGetLastError();
 }
 

@@ -11,7 +11,8 @@ The server
 * advances all active solves together: one tick is one parareal iteration of
   each of them, i.e. one batched fine sweep over every unconverged slice of
   every active solve (`sth_fine_sweep_batched`, all kernel classes
-  concurrent) followed by their corrections;
+  concurrent) followed by their corrections in one launch
+  (`sth_parareal_correct_batched`, one read-back of all errors);
 * retires a solve when it reaches its tolerance or its iteration limit,
   returns the slice-end densities and frees its block, which admits the next
   waiting requests at the next tick.
@@ -169,8 +170,9 @@ class Server:
                 continue
             # one tick: one parareal iteration of every active solve
             sth.sth_fine_sweep_batched([a.prob for a in active], self.stream)
-            for a in active:
-                e, _ = sth.sth_parareal_correct(a.prob, want_err=True, stream=self.stream)
+            errs = sth.sth_parareal_correct_batched([a.prob for a in active], want_err=True,
+                                                    stream=self.stream)
+            for a, e in zip(active, errs):
                 a.errors.append(e)
             self.ticks += 1
             done_t = clock() - t0

@@ -28,7 +28,8 @@ START_LIFT, START_CARRY = 0, 1
 EXPORTS = (
     "sth_footprint_bytes", "sth_create", "sth_coarse_sweep", "sth_fine_sweep_batched",
     "sth_parareal_correct", "sth_moments_criteria", "sth_get_rho", "sth_get_g", "sth_get_info",
-    "sth_fine_run", "sth_destroy", "sth_last_error",
+    "sth_fine_run", "sth_destroy", "sth_last_error", "sth_parareal_correct_batched", "sth_get_errors",
+    "sth_graph_create", "sth_graph_launch", "sth_graph_wait", "sth_graph_destroy",
 )
 
 
@@ -98,6 +99,13 @@ def lib() -> ctypes.CDLL:
         L.sth_get_info.argtypes = [_VP, ctypes.POINTER(Info)]
         L.sth_fine_run.argtypes = [_VP, _D, _D, ctypes.c_longlong, _D, _D,
                                    ctypes.POINTER(ctypes.c_int), _D, _VP]
+        L.sth_parareal_correct_batched.argtypes = [ctypes.POINTER(_VP), ctypes.c_int, _D, _VP]
+        L.sth_get_errors.argtypes = [_VP, _D]
+        L.sth_graph_create.argtypes = [ctypes.POINTER(_VP), ctypes.c_int, ctypes.POINTER(_VP)]
+        L.sth_graph_launch.argtypes = [_VP, _VP]
+        L.sth_graph_wait.argtypes = [_VP, _VP, ctypes.POINTER(ctypes.c_int), _D]
+        L.sth_graph_destroy.argtypes = [_VP]
+        L.sth_graph_destroy.restype = None
         L.sth_destroy.argtypes = [_VP]
         L.sth_destroy.restype = None
         L.sth_last_error.restype = ctypes.c_char_p
@@ -220,6 +228,57 @@ def sth_parareal_correct(p: Problem, want_err: bool = True, stream=None):
     _check(lib().sth_parareal_correct(p.h, ctypes.byref(err) if want_err else None,
                                       ctypes.byref(k), _stream(stream)))
     return (err.value if want_err else None), k.value
+
+
+def sth_parareal_correct_batched(problems: Sequence[Problem], want_err: bool = True, stream=None):
+    """Corrections of several problems in one launch; returns their errors
+    (None when want_err is False)."""
+    arr = (_VP * len(problems))(*[q.h for q in problems])
+    errs = np.zeros(len(problems)) if want_err else None
+    _check(lib().sth_parareal_correct_batched(arr, len(problems), _d(errs), _stream(stream)))
+    return None if errs is None else errs.tolist()
+
+
+def sth_get_errors(p: Problem) -> list:
+    """Successive errors of the iterations done so far."""
+    k = p.info().k_done
+    out = np.zeros(max(k, 1))
+    _check(lib().sth_get_errors(p.h, _d(out)))
+    return out[:k].tolist()
+
+
+class Graph:
+    """Owning handle of an sth_graph: a whole parareal solve of the given
+    problems recorded once and replayed by one launch."""
+
+    def __init__(self, problems: Sequence[Problem]):
+        self.problems = list(problems)
+        arr = (_VP * len(self.problems))(*[q.h for q in self.problems])
+        h = _VP()
+        _check(lib().sth_graph_create(arr, len(self.problems), ctypes.byref(h)))
+        self.h = h
+
+    def launch(self, stream=None) -> None:
+        _check(lib().sth_graph_launch(self.h, _stream(stream)))
+
+    def wait(self, stream=None):
+        """Returns (iterations done, last error) per problem."""
+        n = len(self.problems)
+        iters = (ctypes.c_int * n)()
+        errs = np.zeros(n)
+        _check(lib().sth_graph_wait(self.h, _stream(stream), iters, _d(errs)))
+        return list(iters), errs.tolist()
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().sth_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def sth_moments_criteria(p: Problem, slice_: int, stream=None) -> dict:

@@ -118,6 +118,28 @@ typedef struct {
                                   1, or that of STH_COARSE_EXPLICIT           */
 } sth_info;
 
+/* Launch configuration of the fine kernel for one kernel class: the class
+ * is (precision, nv, nx rounded up to a multiple of 64).  block = threads
+ * per workgroup (one workgroup per slice, ceil(nx/block) <= 4 interfaces per
+ * thread); resident = 1 keeps a slice's rows in registers for the whole
+ * slice, 0 streams them from device memory every step. */
+typedef struct {
+    int block;
+    int resident;
+} sth_fine_config;
+
+/* Every configuration the kernel supports for the class of (precision, nx,
+ * nv); writes at most cap of them to out, the total to *count. */
+int  sth_fine_config_candidates(int precision, int nx, int nv, sth_fine_config *out, int cap, int *count);
+/* Use cfg for the class from now on in this process (all devices, later
+ * sweeps and recorded graphs); NULL returns the class to the default rule
+ * (the largest workgroup, resident when the rows fit).  STH_EINVAL when cfg
+ * is not supported for every nx of the class.  Results do not depend on the
+ * configuration except through the order of the per-step sums. */
+int  sth_set_fine_config(int precision, int nx, int nv, const sth_fine_config *cfg);
+/* The configuration in force for the class of (precision, nx, nv). */
+int  sth_get_fine_config(int precision, int nx, int nv, sth_fine_config *out);
+
 /* Device bytes a problem with this description needs (serving admission).
  * Only sizes are read.  *out receives the byte count. */
 int  sth_footprint_bytes(const sth_problem_desc *d, size_t *out);

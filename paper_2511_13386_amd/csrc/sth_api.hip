@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -158,6 +159,68 @@ int side_pool(SidePool **out)
     }
     *out = &P;
     return STH_OK;
+}
+
+// Launch configurations chosen for kernel classes (sth_set_fine_config),
+// keyed by (precision, nv, nx rounded up to the wavefront).
+struct ClassKey {
+    int prec, nv, nxr;
+    bool operator<(const ClassKey &o) const
+    {
+        return prec != o.prec ? prec < o.prec : (nv != o.nv ? nv < o.nv : nxr < o.nxr);
+    }
+};
+std::mutex g_tune_mu;
+std::map<ClassKey, sth_fine_config> g_tune;
+
+ClassKey class_key(int prec, int nx, int nv) { return {prec, nv, (nx + kWave - 1) / kWave * kWave}; }
+
+// A launch configuration is supported for nx when the workgroup is a
+// multiple of the wavefront no larger than nx rounded up, covers nx with at
+// most kMaxSlabs interfaces per thread, its LDS fits, and (resident) the
+// rows fit in registers.
+bool config_ok(int prec, int nx, int nv, const sth_fine_config &c)
+{
+    const int nxr = (nx + kWave - 1) / kWave * kWave;
+    if (c.block < kWave || c.block > kFineBlock || c.block % kWave || c.block > nxr) return false;
+    if ((nx + c.block - 1) / c.block > kMaxSlabs) return false;
+    const FineShape sh = fine_shape(prec, nx, nv, c.resident ? 0 : 1, c.block);
+    return sh.block == c.block && sh.lds <= kMaxLds && (sh.stream == 0) == (c.resident != 0);
+}
+
+// Candidate configurations for nx: for each count of interfaces per thread
+// (1..kMaxSlabs) the smallest workgroup that covers nx with it, and the
+// largest workgroup; each resident (where supported) and streamed.
+std::vector<sth_fine_config> class_candidates(int prec, int nx, int nv)
+{
+    std::vector<int> blocks;
+    for (int ipt = 1; ipt <= kMaxSlabs; ++ipt) {
+        const int per = (nx + ipt - 1) / ipt;
+        blocks.push_back((per + kWave - 1) / kWave * kWave);
+    }
+    blocks.push_back(std::min(kFineBlock, (nx + kWave - 1) / kWave * kWave));
+    std::sort(blocks.begin(), blocks.end(), [](int a, int b) { return a > b; });
+    blocks.erase(std::unique(blocks.begin(), blocks.end()), blocks.end());
+    std::vector<sth_fine_config> out;
+    for (int b : blocks)
+        for (int res = 1; res >= 0; --res) {
+            const sth_fine_config c{b, res};
+            if (config_ok(prec, nx, nv, c)) out.push_back(c);
+        }
+    return out;
+}
+
+// Shape of the fine kernel for a class: the chosen configuration if one is
+// set, else the default rule.
+FineShape class_shape(int prec, int nx, int nv)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(class_key(prec, nx, nv));
+        if (it != g_tune.end() && config_ok(prec, nx, nv, it->second))
+            return fine_shape(prec, nx, nv, it->second.resident ? 0 : 1, it->second.block);
+    }
+    return fine_shape(prec, nx, nv, 0, 0);
 }
 
 }  // namespace
@@ -317,7 +380,7 @@ struct SweepItem {
 void plan_problem_sweep(sth_problem *p, int k, const std::vector<char> &have_end, const int *stop,
                         std::vector<SweepItem> &items, std::vector<LiftJob> &lifts, std::vector<CopyJob> &copies)
 {
-    const FineShape sh = fine_shape(p->prec, p->nx, p->nv, 0, 0);
+    const FineShape sh = class_shape(p->prec, p->nx, p->nv);
     for (int n = k + 1; n <= p->N; ++n) {
         FineUnit u = make_unit(p, n);
         u.stop = stop;
@@ -924,6 +987,52 @@ int sth_get_errors(const sth_problem *p, double *host_out)
 
 void sth_graph_destroy(sth_graph *g) { destroy_graph(g); }
 
+int sth_fine_config_candidates(int precision, int nx, int nv, sth_fine_config *out, int cap, int *count)
+{
+    if (!count || cap < 0 || (cap > 0 && !out)) return fail(STH_EINVAL, "null argument");
+    if (precision != STH_FP64 && precision != STH_FP32_BULK) return fail(STH_EINVAL, "unknown precision");
+    if (nx < 8 || nx > kMaxNx) return fail(STH_EINVAL, "nx must be in [8, 2048]");
+    if (!(nv == 16 || nv == 32 || nv == 64 || nv == 128)) return fail(STH_EINVAL, "nv must be 16, 32, 64 or 128");
+    const std::vector<sth_fine_config> c = class_candidates(precision == STH_FP64 ? 0 : 1, nx, nv);
+    *count = (int)c.size();
+    for (int i = 0; i < cap && i < (int)c.size(); ++i) out[i] = c[i];
+    return STH_OK;
+}
+
+int sth_set_fine_config(int precision, int nx, int nv, const sth_fine_config *cfg)
+{
+    if (precision != STH_FP64 && precision != STH_FP32_BULK) return fail(STH_EINVAL, "unknown precision");
+    if (nx < 8 || nx > kMaxNx) return fail(STH_EINVAL, "nx must be in [8, 2048]");
+    if (!(nv == 16 || nv == 32 || nv == 64 || nv == 128)) return fail(STH_EINVAL, "nv must be 16, 32, 64 or 128");
+    const int prec = precision == STH_FP64 ? 0 : 1;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (!cfg) {
+        g_tune.erase(class_key(prec, nx, nv));
+        return STH_OK;
+    }
+    // a configuration must be valid for every nx of the class
+    const ClassKey key = class_key(prec, nx, nv);
+    const sth_fine_config c{cfg->block, cfg->resident ? 1 : 0};
+    for (int x = key.nxr - kWave + 1; x <= key.nxr; ++x) {
+        if (x < 8 || x > kMaxNx) continue;
+        if (!config_ok(prec, x, nv, c)) return fail(STH_EINVAL, "launch configuration not supported for this class");
+    }
+    g_tune[key] = c;
+    return STH_OK;
+}
+
+int sth_get_fine_config(int precision, int nx, int nv, sth_fine_config *out)
+{
+    if (!out) return fail(STH_EINVAL, "null argument");
+    if (precision != STH_FP64 && precision != STH_FP32_BULK) return fail(STH_EINVAL, "unknown precision");
+    if (nx < 8 || nx > kMaxNx) return fail(STH_EINVAL, "nx must be in [8, 2048]");
+    if (!(nv == 16 || nv == 32 || nv == 64 || nv == 128)) return fail(STH_EINVAL, "nv must be 16, 32, 64 or 128");
+    const FineShape sh = class_shape(precision == STH_FP64 ? 0 : 1, nx, nv);
+    out->block = sh.block;
+    out->resident = sh.stream ? 0 : 1;
+    return STH_OK;
+}
+
 int sth_moments_criteria(const sth_problem *p, int slice, double *E, double *J, double *Phi, double *N,
                          double *R, int *cell_mask, void *stream)
 {
@@ -988,7 +1097,7 @@ int sth_get_info(const sth_problem *p, sth_info *out)
     out->kinetic_iface_steps = tot;
     out->last_err = p->last_err;
     out->footprint_bytes = p->bytes;
-    const FineShape sh = fine_shape(p->prec, p->nx, p->nv, 0, 0);
+    const FineShape sh = class_shape(p->prec, p->nx, p->nv);
     out->fine_resident = sh.stream ? 0 : 1;
     out->fine_block = sh.block;
     out->coarse_steps = (p->flags & STH_COARSE_EXPLICIT) ? p->coarse_steps : 1;
@@ -1029,7 +1138,7 @@ int sth_fine_run(sth_problem *p, const double *rho_in, const double *g_in, long 
     }
     FineUnit *dt = p->at<FineUnit>(p->L.units);
     HIPCHK(hipMemcpy(dt, &u, sizeof(u), hipMemcpyHostToDevice));
-    const FineShape sh = fine_shape(p->prec, nx, p->nv, 0, 0);
+    const FineShape sh = class_shape(p->prec, nx, p->nv);
     HIPCHK(launch_fine(sh, dt, 1, st));
     HIPCHK(hipStreamSynchronize(st));
     if (rho_out) HIPCHK(hipMemcpy(rho_out, d_rout, sizeof(double) * nx, hipMemcpyDeviceToHost));

@@ -12,6 +12,7 @@ constexpr int kWave = 64;
 constexpr int kMaxNx = 2048;
 constexpr size_t kMaxLds = 160 * 1024;  // LDS bytes of one gfx950 workgroup
 constexpr int kMaxSlabs = 4;          // interfaces per thread (nx <= 2048 with 512 threads)
+constexpr int kFineBlock = 512;       // threads per fine-sweep workgroup at most
 
 // Per-problem constants of the fine propagator (device memory).
 struct FineConst {

@@ -209,7 +209,6 @@ __host__ __device__ inline FineLds fine_lds(int nx, int nv, int realsz, int nslo
 // H[parity][side][segment][HV] (side 0: v<0 half of a segment's first
 // interface, side 1: v>0 half of its last), double-buffered by step parity
 // and kept in global memory, so that the velocity loop touches no LDS.
-constexpr int kFineBlock = 512;  // threads per fine-sweep workgroup at most
 
 // Uniform per-velocity constants are read through the constant address space
 // so that they are scalar loads into SGPRs, not vector registers.

@@ -30,6 +30,7 @@ EXPORTS = (
     "sth_parareal_correct", "sth_moments_criteria", "sth_get_rho", "sth_get_g", "sth_get_info",
     "sth_fine_run", "sth_destroy", "sth_last_error", "sth_parareal_correct_batched", "sth_get_errors",
     "sth_graph_create", "sth_graph_launch", "sth_graph_wait", "sth_graph_destroy",
+    "sth_fine_config_candidates", "sth_set_fine_config", "sth_get_fine_config",
 )
 
 
@@ -65,6 +66,10 @@ class Info(ctypes.Structure):
         ("fine_resident", ctypes.c_int), ("fine_block", ctypes.c_int),
         ("coarse_steps", ctypes.c_longlong),
     ]
+
+
+class FineConfig(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int), ("resident", ctypes.c_int)]
 
 
 _lib = None
@@ -106,6 +111,11 @@ def lib() -> ctypes.CDLL:
         L.sth_graph_wait.argtypes = [_VP, _VP, ctypes.POINTER(ctypes.c_int), _D]
         L.sth_graph_destroy.argtypes = [_VP]
         L.sth_graph_destroy.restype = None
+        L.sth_fine_config_candidates.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                 ctypes.POINTER(FineConfig), ctypes.c_int,
+                                                 ctypes.POINTER(ctypes.c_int)]
+        L.sth_set_fine_config.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(FineConfig)]
+        L.sth_get_fine_config.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(FineConfig)]
         L.sth_destroy.argtypes = [_VP]
         L.sth_destroy.restype = None
         L.sth_last_error.restype = ctypes.c_char_p
@@ -279,6 +289,29 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+def sth_fine_config_candidates(precision: int, nx: int, nv: int) -> list:
+    """[(block, resident)] supported for the class of (precision, nx, nv)."""
+    n = ctypes.c_int()
+    buf = (FineConfig * 16)()
+    _check(lib().sth_fine_config_candidates(int(precision), int(nx), int(nv), buf, 16, ctypes.byref(n)))
+    return [(buf[i].block, buf[i].resident) for i in range(min(n.value, 16))]
+
+
+def sth_set_fine_config(precision: int, nx: int, nv: int, config=None) -> None:
+    """Set (block, resident) for the class, or None for the default rule."""
+    if config is None:
+        _check(lib().sth_set_fine_config(int(precision), int(nx), int(nv), None))
+    else:
+        c = FineConfig(int(config[0]), int(config[1]))
+        _check(lib().sth_set_fine_config(int(precision), int(nx), int(nv), ctypes.byref(c)))
+
+
+def sth_get_fine_config(precision: int, nx: int, nv: int) -> tuple:
+    c = FineConfig()
+    _check(lib().sth_get_fine_config(int(precision), int(nx), int(nv), ctypes.byref(c)))
+    return (c.block, c.resident)
 
 
 def sth_moments_criteria(p: Problem, slice_: int, stream=None) -> dict:

@@ -90,6 +90,8 @@ def parse():
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-T", type=float, default=0.01)
     ap.add_argument("--batch-slices", type=int, default=32)
+    ap.add_argument("--no-autotune", action="store_true", help="batch: keep the default launch configurations")
+    ap.add_argument("--tune-steps", type=int, default=100, help="batch: steps per slice of the tuning sweeps")
     ap.add_argument("--baseline-every", type=int, default=20,
                     help="batch: every n-th instance also runs alone in FP64 (the baseline form)")
     ap.add_argument("--requests", type=int, default=200, help="serve: number of requests")
@@ -157,6 +159,20 @@ def run_batch(args, torch, sth, wl):
                         steps_override=steps_override)
 
     stream = torch.cuda.Stream()
+    tune_info = None
+    if not args.no_autotune:
+        from paper_2511_13386_amd import autotune
+        t0 = time.perf_counter()
+        tuned = autotune.autotune([desc(i, prec) for i in insts], steps=args.tune_steps, repeats=2,
+                                  stream=stream)
+        sp = [r.speedup_over_default for r in tuned.values()]
+        tune_info = {"classes": len(tuned), "seconds": time.perf_counter() - t0,
+                     "changed": sum(r.best != r.default for r in tuned.values()),
+                     "class_speedup_min": min(sp), "class_speedup_max": max(sp),
+                     "class_speedup_geomean": float(np.exp(np.mean(np.log(sp))))}
+        print(f"# autotuned {len(tuned)} classes in {tune_info['seconds']:.1f} s, "
+              f"{tune_info['changed']} changed, speedup {tune_info['class_speedup_geomean']:.3f} geomean",
+              file=sys.stderr, flush=True)
     if args.warmup > 0:  # every kernel class once, short slices
         ws = [sth.Problem(desc(i, prec, steps_override=20)) for i in insts]
         for w in ws:
@@ -169,18 +185,16 @@ def run_batch(args, torch, sth, wl):
 
     def solve(problems, precision_label):
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
-        for p in problems:
-            sth.sth_coarse_sweep(p, stream)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        sth.sth_coarse_sweep_batched(problems, stream)
         for k in range(K):
             with torch.cuda.stream(stream):
                 ev[k][0].record(stream)
             sth.sth_fine_sweep_batched(problems, stream)
             with torch.cuda.stream(stream):
                 ev[k][1].record(stream)
-            for p in problems:
-                sth.sth_parareal_correct(p, want_err=False, stream=stream)
+            sth.sth_parareal_correct_batched(problems, want_err=False, stream=stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         ms = [a.elapsed_time(b) for a, b in ev]
@@ -193,9 +207,24 @@ def run_batch(args, torch, sth, wl):
     rate = kin / (sum(ms) * 1e-3)
     print(f"# batched {len(problems)} instances: {kin:.3e} kinetic cell-updates in {sum(ms):.0f} ms of sweeps",
           file=sys.stderr, flush=True)
-    U_batch = {i: sth.sth_get_rho(problems[i]) for i in range(0, len(insts), args.baseline_every)}
-    mass = max(float(np.max(np.abs(sth.sth_get_rho(p).sum(axis=1) - inst.rho_in.sum())) / abs(inst.rho_in.sum()))
-               for p, inst in zip(problems, insts))
+    U_all = [sth.sth_get_rho(p) for p in problems]
+    U_batch = {i: U_all[i] for i in range(0, len(insts), args.baseline_every)}
+    mass = max(float(np.max(np.abs(U.sum(axis=1) - inst.rho_in.sum())) / abs(inst.rho_in.sum()))
+               for U, inst in zip(U_all, insts))
+    # the same solves recorded once as a HIP graph and replayed by one launch
+    t0 = time.perf_counter()
+    graph = sth.Graph(problems)
+    t_rec = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    graph.launch(stream)
+    graph.wait(stream)
+    graph_wall = time.perf_counter() - t0
+    graph_same = all(np.array_equal(sth.sth_get_rho(p), U) for p, U in zip(problems, U_all))
+    graph.close()
+    print(f"# eager solve {wall:.3f} s, graph replay {graph_wall:.3f} s (recorded in {t_rec:.2f} s), "
+          f"identical: {graph_same}", file=sys.stderr, flush=True)
+    del U_all
     for p in problems:
         p.close()
 
@@ -228,6 +257,10 @@ def run_batch(args, torch, sth, wl):
         "max_rel_rho_diff_vs_single_fp64": max(errs) if errs else None,
         "mass_drift_rel_max": mass,
         "parareal_wall_s": wall,
+        "parareal_wall_s_graph": graph_wall,
+        "graph_record_s": t_rec,
+        "graph_equals_eager": graph_same,
+        "autotune": tune_info,
     }
     print(json.dumps(out), flush=True)
 

@@ -159,6 +159,10 @@ int  sth_create(const sth_problem_desc *d, void *arena, size_t arena_bytes, sth_
  * correction. */
 int  sth_coarse_sweep(sth_problem *p, void *stream);
 
+/* The same coarse guess for several problems in one launch (one workgroup
+ * per problem).  STH_EINVAL if a problem appears twice. */
+int  sth_coarse_sweep_batched(sth_problem *const *p, int count, void *stream);
+
 /* Fine propagator F = S^HMM (scheme of Section 2.3 with the cell rules of
  * Section 2.2) over every unconverged slice n > k of every problem in the
  * batch, all in one batched launch per kernel class: the parallel loop of

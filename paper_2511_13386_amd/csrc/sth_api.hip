@@ -654,6 +654,46 @@ int sth_coarse_sweep(sth_problem *p, void *stream)
     return STH_OK;
 }
 
+int sth_coarse_sweep_batched(sth_problem *const *probs, int count, void *stream)
+{
+    if (count < 0 || (count > 0 && !probs)) return fail(STH_EINVAL, "bad batch");
+    for (int b = 0; b < count; ++b) {
+        if (!probs[b]) return fail(STH_EINVAL, "null problem in batch");
+        for (int c = 0; c < b; ++c)
+            if (probs[c] == probs[b]) return fail(STH_EINVAL, "a problem appears twice in the batch");
+    }
+    if (count == 0) return STH_OK;
+    hipStream_t st = (hipStream_t)stream;
+    int slot = 0;
+    int rc = acquire_table(sizeof(CoarseJob) * (size_t)count, &slot);
+    if (rc) return rc;
+    std::vector<CoarseJob> jobs(count);
+    int block = kWave;
+    size_t lds = 0;
+    for (int b = 0; b < count; ++b) {
+        sth_problem *p = probs[b];
+        jobs[b] = coarse_job_of(p, 0, 0);
+        int bb = 0;
+        size_t ll = 0;
+        coarse_launch_dims(p->nx, (p->flags & STH_COARSE_EXPLICIT) != 0, &bb, &ll);
+        block = std::max(block, bb);
+        lds = std::max(lds, ll);
+    }
+    CoarseJob *tab = (CoarseJob *)g_pool[slot].ptr;
+    HIPCHK(hipMemcpyAsync(tab, jobs.data(), sizeof(CoarseJob) * jobs.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(launch_coarse_many(tab, count, block, lds, st));
+    HIPCHK(hipEventRecord(g_pool[slot].ev, st));
+    g_pool[slot].used = true;
+    for (int b = 0; b < count; ++b) {
+        sth_problem *p = probs[b];
+        p->coarse_done = true;
+        p->k = 0;
+        p->swept = false;
+        std::fill(p->have_end.begin(), p->have_end.end(), 0);
+    }
+    return STH_OK;
+}
+
 int sth_fine_sweep_batched(sth_problem *const *probs, int count, void *stream)
 {
     if (count < 0 || (count > 0 && !probs)) return fail(STH_EINVAL, "bad batch");

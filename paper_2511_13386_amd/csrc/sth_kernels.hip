@@ -1090,9 +1090,11 @@ hipError_t launch_fine(const FineShape &s, const FineUnit *d, int n, hipStream_t
 }
 
 // ------------------------------------------------------------ block helpers
-// Poisson on one workgroup: E[p] from rho (global or LDS), zero-mean gauge.
-// Sequential prefix sum by thread 0 (the macro quantities of the non-hot
-// kernels are O(nx)).
+// Poisson on one workgroup: E[p] from rho (global or LDS), zero-mean gauge,
+// E_p = s_p - mean(s) with s_p = sum_{i<=p} (rho_i - rhobar) dx.  Each thread
+// owns ceil(nx/blockDim) contiguous cells; wavefront DPP scans of the cell
+// sums and of sum_i d_i (nx - i) (= sum_p s_p), then one pass over the wave
+// totals.  blockDim is a multiple of 64, at most 1024.
 __device__ void block_poisson(const double *rho, double *E, int nx, double dx, double rhobar,
                               bool field)
 {
@@ -1101,19 +1103,132 @@ __device__ void block_poisson(const double *rho, double *E, int nx, double dx, d
         __syncthreads();
         return;
     }
-    __shared__ double s_mean;
-    if (threadIdx.x == 0) {
-        double s = 0.0, m = 0.0;
-        for (int p = 0; p < nx; ++p) {
-            s += (rho[p] - rhobar) * dx;
-            E[p] = s;
-            m += s;
-        }
-        s_mean = m / (double)nx;
+    __shared__ double s_wt[2][16];
+    const int BS = blockDim.x, t = threadIdx.x, lane = t & (kWave - 1), wid = t / kWave;
+    const int NW = (BS + kWave - 1) / kWave;
+    const int q = (nx + BS - 1) / BS, i0 = t * q;
+    double own = 0.0, wsum = 0.0;
+    for (int u = 0; u < q; ++u) {
+        const int i = i0 + u;
+        const double d = i < nx ? (rho[i] - rhobar) * dx : 0.0;
+        own += d;
+        wsum += i < nx ? d * (double)(nx - i) : 0.0;
+    }
+    double a = own, b = wsum;
+    wave_scan2_f64(a, b);
+    if (lane == kWave - 1) {
+        s_wt[0][wid] = a;
+        s_wt[1][wid] = b;
     }
     __syncthreads();
-    const double m = s_mean;
-    for (int p = threadIdx.x; p < nx; p += blockDim.x) E[p] -= m;
+    double off = 0.0, Wtot = 0.0;
+    for (int w = 0; w < NW; ++w) {
+        off += w < wid ? s_wt[0][w] : 0.0;
+        Wtot += s_wt[1][w];
+    }
+    const double mean = Wtot / (double)nx;
+    double run = off + (a - own);
+    for (int u = 0; u < q; ++u) {
+        const int i = i0 + u;
+        if (i < nx) {
+            run += (rho[i] - rhobar) * dx;
+            E[i] = run - mean;
+        }
+    }
+    __syncthreads();
+}
+
+// Cyclic tridiagonal solve a_i x_{i-1} + b_i x_i + c_i x_{i+1} = d_i
+// (indices mod n, 8 <= n <= 2048, diagonally dominant) by the first
+// wavefront of the workgroup; every thread of the workgroup calls it.
+// Partition method: lane p owns a contiguous block of m >= 2 rows; the
+// interior rows of its block (all but the last) are eliminated by Thomas
+// with three right-hand sides, which expresses them through the last rows
+// l_{p-1} (previous block) and l_p; substituting into the equations of the
+// last rows leaves a cyclic tridiagonal system for l_0..l_{P-1}, solved by
+// one lane with Thomas and the Sherman-Morrison correction, then every lane
+// reconstructs its rows.  Y, U, V, cp: [n] scratch; x may alias V.
+__device__ void cyclic_tridiag_block(const double *a, const double *b, const double *c, const double *d,
+                                     double *x, double *Y, double *U, double *V, double *cp, int n)
+{
+    __shared__ double s_red[8][kWave];
+    double *rA = s_red[0], *rB = s_red[1], *rC = s_red[2], *rD = s_red[3];
+    double *rL = s_red[4], *rcp = s_red[5], *rdp = s_red[6], *rz = s_red[7];
+    const int t = threadIdx.x;
+    const int P = min(kWave, n / 2);
+    const int base = n / P, rem = n % P;
+    auto first_row = [&](int p) { return p * base + min(p, rem); };
+    // interior elimination (rows r0 .. last-1), three right-hand sides
+    if (t < P) {
+        const int r0 = first_row(t), k = base + (t < rem ? 1 : 0) - 1;
+        double den = b[r0];
+        cp[r0] = c[r0] / den;
+        Y[r0] = d[r0] / den;
+        U[r0] = -a[r0] / den;
+        V[r0] = (k == 1 ? -c[r0] : 0.0) / den;
+        for (int i = 1; i < k; ++i) {
+            const int row = r0 + i;
+            den = b[row] - a[row] * cp[row - 1];
+            cp[row] = c[row] / den;
+            Y[row] = (d[row] - a[row] * Y[row - 1]) / den;
+            U[row] = (-a[row] * U[row - 1]) / den;
+            V[row] = ((i == k - 1 ? -c[row] : 0.0) - a[row] * V[row - 1]) / den;
+        }
+        for (int i = k - 2; i >= 0; --i) {
+            const int row = r0 + i;
+            Y[row] -= cp[row] * Y[row + 1];
+            U[row] -= cp[row] * U[row + 1];
+            V[row] -= cp[row] * V[row + 1];
+        }
+    }
+    __syncthreads();
+    // reduced system of the last rows
+    if (t < P) {
+        const int r0 = first_row(t), last = r0 + base + (t < rem ? 1 : 0) - 1, il = last - 1;
+        const int f = first_row(t + 1 == P ? 0 : t + 1);
+        const double al = a[last], cl = c[last];
+        rA[t] = al * U[il];
+        rB[t] = al * V[il] + b[last] + cl * U[f];
+        rC[t] = cl * V[f];
+        rD[t] = d[last] - al * Y[il] - cl * Y[f];
+    }
+    __syncthreads();
+    if (t == 0) {
+        // Thomas on the matrix with the corner terms moved into a rank-one
+        // update u v^T, u = (gamma, 0, .., 0, C_{P-1}), v = (1, 0, .., 0, A_0/gamma)
+        const double gamma = -rB[0];
+        const double b0 = rB[0] - gamma;
+        const double bl = rB[P - 1] - rA[0] * rC[P - 1] / gamma;
+        double m = b0;
+        rcp[0] = rC[0] / m;
+        rdp[0] = rD[0] / m;
+        rz[0] = gamma / m;
+        for (int i = 1; i < P; ++i) {
+            const double bi = (i == P - 1) ? bl : rB[i];
+            m = bi - rA[i] * rcp[i - 1];
+            rcp[i] = rC[i] / m;
+            rdp[i] = (rD[i] - rA[i] * rdp[i - 1]) / m;
+            const double ui = (i == P - 1) ? rC[P - 1] : 0.0;
+            rz[i] = (ui - rA[i] * rz[i - 1]) / m;
+        }
+        rL[P - 1] = rdp[P - 1];
+        for (int i = P - 2; i >= 0; --i) {
+            rL[i] = rdp[i] - rcp[i] * rL[i + 1];
+            rz[i] = rz[i] - rcp[i] * rz[i + 1];
+        }
+        const double fact = (rL[0] + rA[0] * rL[P - 1] / gamma) / (1.0 + rz[0] + rA[0] * rz[P - 1] / gamma);
+        for (int i = 0; i < P; ++i) rL[i] -= fact * rz[i];
+    }
+    __syncthreads();
+    if (t < P) {
+        const int r0 = first_row(t), k = base + (t < rem ? 1 : 0) - 1;
+        const double lp = rL[t == 0 ? P - 1 : t - 1], lo = rL[t];
+        for (int i = 0; i < k; ++i) {
+            const int row = r0 + i;
+            x[row] = Y[row] + U[row] * lp + V[row] * lo;
+        }
+        x[r0 + k] = lo;
+    }
     __syncthreads();
 }
 
@@ -1251,32 +1366,7 @@ __device__ void coarse_step_block(const FineConst *C, const double *rin, double 
         c[i] = -alpha + beta * Ee;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        const double gamma = -b[0];
-        const double b0 = b[0] - gamma;
-        const double bl = b[nx - 1] - a[0] * c[nx - 1] / gamma;
-        // Thomas on the modified matrix for two right-hand sides (rho, u)
-        double m = b0;
-        cp[0] = c[0] / m;
-        dp[0] = rin[0] / m;
-        z[0] = gamma / m;  // forward sweep of u = (gamma, 0, ..., 0, c_{n-1})
-        for (int i = 1; i < nx; ++i) {
-            const double bi = (i == nx - 1) ? bl : b[i];
-            m = bi - a[i] * cp[i - 1];
-            cp[i] = c[i] / m;
-            dp[i] = (rin[i] - a[i] * dp[i - 1]) / m;
-            const double ui = (i == nx - 1) ? c[nx - 1] : 0.0;
-            z[i] = (ui - a[i] * z[i - 1]) / m;
-        }
-        x[nx - 1] = dp[nx - 1];
-        for (int i = nx - 2; i >= 0; --i) {
-            x[i] = dp[i] - cp[i] * x[i + 1];
-            z[i] = z[i] - cp[i] * z[i + 1];
-        }
-        const double fact = (x[0] + a[0] * x[nx - 1] / gamma) / (1.0 + z[0] + a[0] * z[nx - 1] / gamma);
-        for (int i = 0; i < nx; ++i) x[i] -= fact * z[i];
-    }
-    __syncthreads();
+    cyclic_tridiag_block(a, b, c, rin, x, dp, z, x, cp, nx);
     // conservative form: flux of the solution, then rho_in + dtG m2 dJ/dx
     for (int p = threadIdx.x; p < nx; p += blockDim.x) {
         const int q = wrapi(p + 1, nx);

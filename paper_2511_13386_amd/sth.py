@@ -31,6 +31,7 @@ EXPORTS = (
     "sth_fine_run", "sth_destroy", "sth_last_error", "sth_parareal_correct_batched", "sth_get_errors",
     "sth_graph_create", "sth_graph_launch", "sth_graph_wait", "sth_graph_destroy",
     "sth_fine_config_candidates", "sth_set_fine_config", "sth_get_fine_config",
+    "sth_coarse_sweep_batched",
 )
 
 
@@ -96,6 +97,7 @@ def lib() -> ctypes.CDLL:
         L.sth_create.argtypes = [ctypes.POINTER(ProblemDesc), _VP, ctypes.c_size_t, ctypes.POINTER(_VP)]
         L.sth_coarse_sweep.argtypes = [_VP, _VP]
         L.sth_fine_sweep_batched.argtypes = [ctypes.POINTER(_VP), ctypes.c_int, _VP]
+        L.sth_coarse_sweep_batched.argtypes = [ctypes.POINTER(_VP), ctypes.c_int, _VP]
         L.sth_parareal_correct.argtypes = [_VP, _D, ctypes.POINTER(ctypes.c_int), _VP]
         L.sth_moments_criteria.argtypes = [_VP, ctypes.c_int, _D, _D, _D, _D, _D,
                                            ctypes.POINTER(ctypes.c_int), _VP]
@@ -225,6 +227,11 @@ def sth_create(desc: Desc, arena=None) -> Problem:
 
 def sth_coarse_sweep(p: Problem, stream=None) -> None:
     _check(lib().sth_coarse_sweep(p.h, _stream(stream)))
+
+
+def sth_coarse_sweep_batched(problems: Sequence[Problem], stream=None) -> None:
+    arr = (_VP * len(problems))(*[q.h for q in problems])
+    _check(lib().sth_coarse_sweep_batched(arr, len(problems), _stream(stream)))
 
 
 def sth_fine_sweep_batched(problems: Sequence[Problem], stream=None) -> None:

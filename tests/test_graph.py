@@ -47,13 +47,15 @@ def _eager(desc):
     return p, errs
 
 
-def test_batched_correction_equals_single():
+def test_batched_coarse_and_correction_equal_single():
     ds = _descs()
     single = [sth.Problem(d) for d in ds]
     batched = [sth.Problem(d) for d in ds]
-    for group in (single, batched):
-        for q in group:
-            sth.sth_coarse_sweep(q)
+    for q in single:
+        sth.sth_coarse_sweep(q)
+    sth.sth_coarse_sweep_batched(batched)
+    for q1, q2 in zip(single, batched):
+        assert np.array_equal(sth.sth_get_rho(q1), sth.sth_get_rho(q2))
     for it in range(2):
         sth.sth_fine_sweep_batched(single)
         e1 = [sth.sth_parareal_correct(q)[0] for q in single]

@@ -83,6 +83,8 @@ def parse():
     ap.add_argument("--T", type=float, default=1.0)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-other-precision", action="store_true",
+                    help="config2: skip the same solve in the other precision")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--workload", choices=["config2", "batch", "serve", "convergence"], default="config2",
                     help="config2: the hybrid parareal problem the metric is quoted on; "
@@ -407,12 +409,12 @@ def main():
     inst = wl.config2(seed=args.seed, nx=args.nx, nv=args.nv, N=args.slices, T=args.T,
                       K=args.steps)
 
-    def desc(steps_override=0):
+    def desc(steps_override=0, precision=prec):
         return sth.Desc(nx=inst.nx, nv=inst.nv, eps_iface=inst.eps_iface, eps_cell=inst.eps_cell,
                         rho0=inst.rho_in, T=inst.T, n_slices=inst.N, k_max=max(args.steps, 1),
                         tol=0.0, eta0=inst.eta0, delta0=inst.delta0, lift_order=1,
                         start_mode=sth.START_CARRY, cfl_theta=inst.theta,
-                        flags=sth.FIELD | sth.HYBRID, precision=prec,
+                        flags=sth.FIELD | sth.HYBRID, precision=precision,
                         steps_override=steps_override)
 
     stream = torch.cuda.Stream()
@@ -533,6 +535,44 @@ def main():
         torch.neg(x, out=y)
         torch.cuda.synchronize()
         out["copy_calibration"] = {"kernel": "torch.neg float32", "read_bytes": 1 << 30, "write_bytes": 1 << 30}
+    if not args.no_other_precision:
+        # the same solve in the other precision (FP32 bulk against FP64)
+        prec2 = sth.FP32_BULK if prec == sth.FP64 else sth.FP64
+        q = sth.Problem(desc(precision=prec2))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sth.sth_coarse_sweep(q, stream)
+        ms2 = []
+        for k in range(K):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            with torch.cuda.stream(stream):
+                a.record(stream)
+            sth.sth_fine_sweep_batched([q], stream)
+            with torch.cuda.stream(stream):
+                b.record(stream)
+            sth.sth_parareal_correct(q, want_err=False, stream=stream)
+            b.synchronize()
+            ms2.append(a.elapsed_time(b))
+        torch.cuda.synchronize()
+        el2 = time.perf_counter() - t0
+        info2 = q.info()
+        U2 = sth.sth_get_rho(q)
+        q.close()
+        v2 = info2.kinetic_iface_steps * inst.nv / (sum(ms2) * 1e-3)
+        v1 = cell_updates / (sum(sweep_ms) * 1e-3)
+        out["fp32_bulk" if prec2 == sth.FP32_BULK else "fp64"] = {
+            "value": v2, "unit": "cell-updates/s (over the fine sweeps)",
+            "value_this_precision_same_measure": v1,
+            "speedup_fp32_over_fp64": v2 / v1 if prec2 == sth.FP32_BULK else v1 / v2,
+            "fine_step_us": float(np.mean(ms2)) * 1e3 / info2.steps_per_slice,
+            "parareal_wall_s": el2,
+            "max_rel_rho_diff": float(np.max(np.abs(U2 - U)) / np.max(np.abs(U))),
+            "mass_drift_rel": float(np.max(np.abs(U2.sum(axis=1) - m0)) / m0),
+            "fine_form": "resident rows" if info2.fine_resident else "streamed rows",
+        }
+        print(f"# other precision: {v2:.3e} cell-updates/s, rho diff "
+              f"{out['fp32_bulk' if prec2 == sth.FP32_BULK else 'fp64']['max_rel_rho_diff']:.2e}",
+              file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst, args.cpu_seconds)
     print(json.dumps(out), flush=True)

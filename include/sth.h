@@ -121,8 +121,9 @@ typedef struct {
 /* Launch configuration of the fine kernel for one kernel class: the class
  * is (precision, nv, nx rounded up to a multiple of 64).  block = threads
  * per workgroup (one workgroup per slice, ceil(nx/block) <= 4 interfaces per
- * thread); resident = 1 keeps a slice's rows in registers for the whole
- * slice, 0 streams them from device memory every step. */
+ * thread; at most 512, or 1024 for the streamed form in FP32 bulk and in
+ * FP64 with nv = 32); resident = 1 keeps a slice's rows in registers for the
+ * whole slice, 0 streams them from device memory every step. */
 typedef struct {
     int block;
     int resident;
@@ -133,7 +134,8 @@ typedef struct {
 int  sth_fine_config_candidates(int precision, int nx, int nv, sth_fine_config *out, int cap, int *count);
 /* Use cfg for the class from now on in this process (all devices, later
  * sweeps and recorded graphs); NULL returns the class to the default rule
- * (the largest workgroup, resident when the rows fit).  STH_EINVAL when cfg
+ * (512 threads, resident when the rows fit; streamed rows beyond 512
+ * interfaces take the 1024-thread workgroup where it exists).  STH_EINVAL when cfg
  * is not supported for every nx of the class.  Results do not depend on the
  * configuration except through the order of the per-step sums. */
 int  sth_set_fine_config(int precision, int nx, int nv, const sth_fine_config *cfg);

@@ -182,15 +182,17 @@ ClassKey class_key(int prec, int nx, int nv) { return {prec, nv, (nx + kWave - 1
 bool config_ok(int prec, int nx, int nv, const sth_fine_config &c)
 {
     const int nxr = (nx + kWave - 1) / kWave * kWave;
-    if (c.block < kWave || c.block > kFineBlock || c.block % kWave || c.block > nxr) return false;
-    if ((nx + c.block - 1) / c.block > kMaxSlabs) return false;
+    const int bmax = (!c.resident && fine_wide_ok(prec, nv)) ? kWideBlock : kFineBlock;
+    if (c.block < kWave || c.block > bmax || c.block % kWave || c.block > nxr) return false;
+    if ((nx + c.block - 1) / c.block > (c.block > kFineBlock ? 2 : kMaxSlabs)) return false;
     const FineShape sh = fine_shape(prec, nx, nv, c.resident ? 0 : 1, c.block);
     return sh.block == c.block && sh.lds <= kMaxLds && (sh.stream == 0) == (c.resident != 0);
 }
 
 // Candidate configurations for nx: for each count of interfaces per thread
 // (1..kMaxSlabs) the smallest workgroup that covers nx with it, and the
-// largest workgroup; each resident (where supported) and streamed.
+// largest workgroups of both kinds; each resident (where supported) and
+// streamed.
 std::vector<sth_fine_config> class_candidates(int prec, int nx, int nv)
 {
     std::vector<int> blocks;
@@ -199,6 +201,7 @@ std::vector<sth_fine_config> class_candidates(int prec, int nx, int nv)
         blocks.push_back((per + kWave - 1) / kWave * kWave);
     }
     blocks.push_back(std::min(kFineBlock, (nx + kWave - 1) / kWave * kWave));
+    blocks.push_back(std::min(kWideBlock, (nx + kWave - 1) / kWave * kWave));
     std::sort(blocks.begin(), blocks.end(), [](int a, int b) { return a > b; });
     blocks.erase(std::unique(blocks.begin(), blocks.end()), blocks.end());
     std::vector<sth_fine_config> out;

@@ -12,7 +12,8 @@ constexpr int kWave = 64;
 constexpr int kMaxNx = 2048;
 constexpr size_t kMaxLds = 160 * 1024;  // LDS bytes of one gfx950 workgroup
 constexpr int kMaxSlabs = 4;          // interfaces per thread (nx <= 2048 with 512 threads)
-constexpr int kFineBlock = 512;       // threads per fine-sweep workgroup at most
+constexpr int kFineBlock = 512;       // threads per fine-sweep workgroup (default form)
+constexpr int kWideBlock = 1024;      // wide workgroups of the streamed form (chosen per class)
 
 // Per-problem constants of the fine propagator (device memory).
 struct FineConst {
@@ -72,6 +73,8 @@ struct FineShape {
 };
 
 FineShape fine_shape(int prec, int nx, int nv, int force_stream, int force_block);
+// The streamed kernel of this class exists with kWideBlock threads.
+bool fine_wide_ok(int prec, int nv);
 hipError_t launch_fine(const FineShape &s, const FineUnit *d_units, int nunits, hipStream_t st);
 
 // Lifting L^L of rho at interfaces into a v-major Real array.

@@ -322,9 +322,13 @@ struct RowIO {
 // two chunks (a straight run of chunks lets the compiler stretch live
 // ranges across them).
 // FP32 rows take half the registers, so their chunks are twice as long
-// (twice the loads in flight) on the wider grids.
-template <typename Real, int NV>
-constexpr int pair_chunk_len() { return NV == 32 ? 2 : (NV >= 64 && sizeof(Real) == 4 ? 8 : 4); }
+// (twice the loads in flight) on the wider grids, except in workgroups of
+// kWideBlock threads, whose lanes have 128 registers at most.
+template <typename Real, int NV, int BLK>
+constexpr int pair_chunk_len()
+{
+    return NV == 32 ? 2 : (NV >= 64 && sizeof(Real) == 4 && BLK <= kFineBlock ? 8 : 4);
+}
 template <typename Real, int CH>
 struct PairBuf {
     Real wn[CH], wp[CH], hn[CH], hp[CH];
@@ -409,11 +413,11 @@ __device__ __forceinline__ void pair_chunk(int t0, const RowIO &io, const RowCoe
 // One row (interface) of a wavefront segment: every velocity pair, chunk by
 // chunk.  first/last: the lane is the first / last valid interface of its
 // segment (it writes the halos of its segment).
-template <typename Real, int NV, bool RAGGED>
+template <typename Real, int NV, bool RAGGED, int CH>
 __device__ __forceinline__ RowOut<Real> row_pass(const RowIO &io, const RowCoef<Real> &c, bool first, bool last,
                                                  ConstPtr<Real> vt)
 {
-    constexpr int HV = NV / 2, CH = pair_chunk_len<Real, NV>();
+    constexpr int HV = NV / 2;
     constexpr unsigned R = sizeof(Real);
     RowOut<Real> o{0, 0, 0};
     PairBuf<Real, CH> A, B;
@@ -520,9 +524,10 @@ __device__ __forceinline__ RowOut<Real> row_pass_res(Real (&Wr)[NV], const RowCo
 // RES: resident form (rows in registers, halos and c1 in LDS), for units
 // whose rows fit in the registers of their lanes; otherwise the rows stream
 // from the unit slot every step.
-template <typename Real, int NV, int IPTM, bool RES>
-__global__ void __launch_bounds__(kFineBlock) k_fine(const FineUnit *__restrict__ units)
+template <typename Real, int NV, int IPTM, bool RES, int BLK>
+__global__ void __launch_bounds__(BLK) k_fine(const FineUnit *__restrict__ units)
 {
+    constexpr int CH = pair_chunk_len<Real, NV, BLK>();
     constexpr int HV = NV / 2;
     extern __shared__ __align__(16) unsigned char smem[];
 
@@ -961,8 +966,8 @@ __global__ void __launch_bounds__(kFineBlock) k_fine(const FineUnit *__restrict_
                     io.hno = (unsigned)(hoff + HALO(npar, 0, seg)) * R;
                     io.hpo = (unsigned)(hoff + HALO(npar, 1, seg)) * R;
                     const ConstPtr<Real> vt = opaque(vtr);
-                    return last == kWave - 1 ? row_pass<Real, NV, false>(io, c, lane == 0, lane == last, vt)
-                                             : row_pass<Real, NV, true>(io, c, lane == 0, lane == last, vt);
+                    return last == kWave - 1 ? row_pass<Real, NV, false, CH>(io, c, lane == 0, lane == last, vt)
+                                             : row_pass<Real, NV, true, CH>(io, c, lane == 0, lane == last, vt);
                 });
             }
         }
@@ -1013,6 +1018,8 @@ __host__ __device__ constexpr bool fine_resident_fits(int realsz, int iptm, int 
 
 static int fine_iptm(int ipt) { return ipt <= 2 ? ipt : 4; }
 
+bool fine_wide_ok(int prec, int nv) { return prec == 1 || nv == 32; }
+
 FineShape fine_shape(int prec, int nx, int nv, int force_stream, int force_block)
 {
     FineShape s{};
@@ -1021,22 +1028,33 @@ FineShape fine_shape(int prec, int nx, int nv, int force_stream, int force_block
     const int realsz = prec == 0 ? 8 : 4;
     int nxr = ((nx + kWave - 1) / kWave) * kWave;
     int b = force_block > 0 ? force_block : kFineBlock;
-    if (b > kFineBlock) b = kFineBlock;
+    // wide workgroups: streamed rows only, in the classes whose streamed
+    // kernel fits 128 registers per lane
+    const bool wide = b > kFineBlock && force_stream && fine_wide_ok(prec, nv);
+    if (b > (wide ? kWideBlock : kFineBlock)) b = wide ? kWideBlock : kFineBlock;
     if (b > nxr) b = nxr;
     s.block = b;
     s.ipt = (nx + b - 1) / b;
     const int nslot = s.ipt * (s.block / kWave);
-    const bool res = !force_stream && s.ipt <= kMaxSlabs && fine_resident_fits(realsz, fine_iptm(s.ipt), nv) &&
+    const bool res = !force_stream && s.block <= kFineBlock && s.ipt <= kMaxSlabs &&
+                     fine_resident_fits(realsz, fine_iptm(s.ipt), nv) &&
                      fine_lds(nx, nv, realsz, nslot, true).total <= kMaxLds;
     s.stream = res ? 0 : 1;
     s.lds = fine_lds(nx, nv, realsz, nslot, res).total;
+    if (!res && force_block <= 0 && nxr > kFineBlock && fine_wide_ok(prec, nv)) {
+        // default for streamed rows beyond 512 interfaces: the wide workgroup
+        // (twice the wavefronts per CU to cover the row loads)
+        s.block = std::min(kWideBlock, nxr);
+        s.ipt = (nx + s.block - 1) / s.block;
+        s.lds = fine_lds(nx, nv, realsz, s.ipt * (s.block / kWave), false).total;
+    }
     return s;
 }
 
-template <typename Real, int NV, int IPT, bool RES>
+template <typename Real, int NV, int IPT, bool RES, int BLK>
 static hipError_t launch_one(const FineShape &s, const FineUnit *d, int n, hipStream_t st)
 {
-    auto kern = k_fine<Real, NV, IPT, RES>;
+    auto kern = k_fine<Real, NV, IPT, RES, BLK>;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)s.lds);
     if (e != hipSuccess) return e;
@@ -1047,12 +1065,18 @@ static hipError_t launch_one(const FineShape &s, const FineUnit *d, int n, hipSt
 template <typename Real, int NV, int IPT>
 static hipError_t launch_form(const FineShape &s, const FineUnit *d, int n, hipStream_t st)
 {
+    if (s.block > kFineBlock) {
+        if constexpr (IPT <= 2 && (sizeof(Real) == 4 || NV == 32)) {
+            if (s.stream && s.block <= kWideBlock) return launch_one<Real, NV, IPT, false, kWideBlock>(s, d, n, st);
+        }
+        return hipErrorInvalidValue;
+    }
     if constexpr (fine_resident_fits((int)sizeof(Real), IPT, NV)) {
-        if (!s.stream) return launch_one<Real, NV, IPT, true>(s, d, n, st);
+        if (!s.stream) return launch_one<Real, NV, IPT, true, kFineBlock>(s, d, n, st);
     } else {
         if (!s.stream) return hipErrorInvalidValue;
     }
-    return launch_one<Real, NV, IPT, false>(s, d, n, st);
+    return launch_one<Real, NV, IPT, false, kFineBlock>(s, d, n, st);
 }
 
 template <typename Real, int NV>
@@ -1070,7 +1094,7 @@ static hipError_t launch_nv(const FineShape &s, const FineUnit *d, int n, hipStr
 hipError_t launch_fine(const FineShape &s, const FineUnit *d, int n, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
-    if (s.ipt > kMaxSlabs || s.block % kWave != 0) return hipErrorInvalidValue;
+    if (s.ipt > kMaxSlabs || s.block % kWave != 0 || s.block > kWideBlock) return hipErrorInvalidValue;
     if (s.prec == 0) {
         switch (s.nv) {
             case 16: return launch_nv<double, 16>(s, d, n, st);

@@ -30,9 +30,11 @@ def test_candidates_are_supported_and_include_the_default(prec, nx, nv):
     assert cands and len(set(cands)) == len(cands)
     assert sth.sth_get_fine_config(prec, nx, nv) in cands
     nxr = (nx + 63) // 64 * 64
+    wide_ok = prec == sth.FP32_BULK or nv == 32
     for block, resident in cands:
-        assert block % 64 == 0 and 64 <= block <= min(512, nxr)
-        assert -(-nx // block) <= 4
+        assert block % 64 == 0 and 64 <= block <= nxr
+        assert block <= (1024 if (wide_ok and not resident) else 512)
+        assert -(-nx // block) <= (2 if block > 512 else 4)
         assert resident in (0, 1)
     # the streamed form exists for every workgroup size
     blocks = {b for b, _ in cands}
@@ -59,6 +61,15 @@ def test_set_get_reset_and_validation(clean_table):
         sth.sth_set_fine_config(sth.FP64, 512, 32, (100, 0))     # not a wavefront multiple
     with pytest.raises(sth.StHError):
         sth.sth_set_fine_config(sth.FP64, 96, 32, (256, 0))      # larger than nx rounded up
+    with pytest.raises(sth.StHError):
+        sth.sth_set_fine_config(sth.FP64, 2048, 64, (1024, 0))   # no wide FP64 kernel for nv = 64
+    with pytest.raises(sth.StHError):
+        sth.sth_set_fine_config(sth.FP32_BULK, 2048, 64, (1024, 1))  # wide workgroups stream rows
+    with pytest.raises(sth.StHError):
+        sth.sth_set_fine_config(sth.FP32_BULK, 2048, 64, (704, 0))   # 3 interfaces per thread
+    sth.sth_set_fine_config(sth.FP32_BULK, 2048, 64, (1024, 0))
+    clean_table.append((sth.FP32_BULK, 2048, 64))
+    assert sth.sth_get_fine_config(sth.FP32_BULK, 2048, 64) == (1024, 0)
 
 
 def test_classes_and_saved_results_round_trip(tmp_path, clean_table):
@@ -85,6 +96,8 @@ def test_classes_and_saved_results_round_trip(tmp_path, clean_table):
     (300, 64, sth.FP32_BULK, 400),   # workgroups of 3 and 5 wavefronts
     (1100, 16, sth.FP64, 150),       # 3 and 4 interfaces per thread, resident
     (512, 128, sth.FP32_BULK, 150),  # streamed with 1..4 interfaces per thread
+    (1100, 64, sth.FP32_BULK, 150),  # wide workgroups (576 and 1024 threads)
+    (1100, 32, sth.FP64, 150),       # wide FP64 workgroups
 ])
 def test_every_candidate_matches_the_oracle(orc, clean_table, nx, nv, prec, steps):
     inst = wl.small_hybrid(nx=nx, nv=nv)

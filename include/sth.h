@@ -171,6 +171,20 @@ int  sth_coarse_sweep_batched(sth_problem *const *p, int count, void *stream);
  * Algorithm 1.  Slice-start perturbations follow start_mode. */
 int  sth_fine_sweep_batched(sth_problem *const *p, int count, void *stream);
 
+/* The same fine sweep advanced in chunks of at most max_steps fine steps per
+ * slice, so that a caller can interleave other work between chunks (the
+ * serving loop batches solves per chunk).  A call starts the sweep of every
+ * problem that has none in progress (slice starts as above), then runs the
+ * next chunk of steps of every slice of every problem in one launch per
+ * kernel class; a suspended slice keeps its state in the problem's memory
+ * (its rows, lazy projection and halos in the slice's slot, its
+ * macroscopic state in a checkpoint).  done_out[count] (optional) receives
+ * 1 for each problem whose sweep has ended (in this call or an earlier one)
+ * and awaits its correction; such problems are not swept again.  The results equal those of sth_fine_sweep_batched bit
+ * for bit, whatever the chunk lengths.  sth_fine_sweep_batched refuses a
+ * problem with a chunked sweep in progress (STH_ESTATE). */
+int  sth_fine_sweep_chunk(sth_problem *const *p, int count, long long max_steps, int *done_out, void *stream);
+
 /* Sequential correction of Algorithm 1 with the new coarse value:
  * U^{k+1}_{k+1} = F^{k+1}, U^n_{k+1} = G(U^{n-1}_{k+1}) + F^n - G(U^{n-1}_k)
  * for n > k+1, then k := k+1.  When err_out is non-NULL the call

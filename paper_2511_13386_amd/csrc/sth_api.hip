@@ -44,7 +44,7 @@ size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 // Device layout of one problem (offsets from the arena base).
 struct Layout {
     size_t cst, eps_p, eps_c, e_p, a_p, vtab, vrow64, vrow32, U, Gc, Fv, err, errh, ctl, work, kin, mask, g0, gend,
-        gst, units, lifts, total;
+        gst, ckpt, units, lifts, total;
 };
 
 Layout layout(int nx, int nv, int N, int realsz)
@@ -72,6 +72,7 @@ Layout layout(int nx, int nv, int N, int realsz)
     L.g0 = o;    o = al256(o + gsz);
     L.gend = o;  o = al256(o + gsz * (size_t)(N + 1));
     L.gst = o;   o = al256(o + gsz * (size_t)(N + 1));
+    L.ckpt = o;  o = al256(o + sizeof(double) * kCkptArrays * (size_t)nx * (size_t)(N + 1));
     L.units = o; o = al256(o + sizeof(FineUnit) * (size_t)(N + 1));
     L.lifts = o; o = al256(o + sizeof(LiftJob) * (size_t)(N + 1));
     L.total = o;
@@ -243,6 +244,8 @@ struct sth_problem {
     bool has_g0 = false;
     std::vector<char> have_end;  // slice n has an end-of-slice perturbation
     double last_err = -1.0;
+    long long chunk_pos = -1;    // next step of a chunked sweep in progress (-1: none)
+    std::vector<FineUnit> chunk_units;
 
     template <typename T>
     T *at(size_t off) const { return (T *)(base + off); }
@@ -365,6 +368,7 @@ FineUnit make_unit(const sth_problem *p, int n)
     u.kin = p->at<unsigned long long>(p->L.kin) + n;
     u.mask_out = nullptr;
     u.nsteps = p->ns;
+    u.ckpt = p->at<double>(p->L.ckpt) + (size_t)n * kCkptArrays * p->nx;
     return u;
 }
 
@@ -653,6 +657,7 @@ int sth_coarse_sweep(sth_problem *p, void *stream)
     p->coarse_done = true;
     p->k = 0;
     p->swept = false;
+    p->chunk_pos = -1;
     std::fill(p->have_end.begin(), p->have_end.end(), 0);
     return STH_OK;
 }
@@ -692,6 +697,7 @@ int sth_coarse_sweep_batched(sth_problem *const *probs, int count, void *stream)
         p->coarse_done = true;
         p->k = 0;
         p->swept = false;
+        p->chunk_pos = -1;
         std::fill(p->have_end.begin(), p->have_end.end(), 0);
     }
     return STH_OK;
@@ -704,6 +710,7 @@ int sth_fine_sweep_batched(sth_problem *const *probs, int count, void *stream)
     for (int b = 0; b < count; ++b) {
         if (!probs[b]) return fail(STH_EINVAL, "null problem in batch");
         if (!probs[b]->coarse_done) return fail(STH_ESTATE, "sth_coarse_sweep must precede the fine sweep");
+        if (probs[b]->chunk_pos >= 0) return fail(STH_ESTATE, "a chunked fine sweep is in progress");
     }
     std::vector<SweepItem> items;
     for (int b = 0; b < count; ++b) {
@@ -738,6 +745,76 @@ int sth_fine_sweep_batched(sth_problem *const *probs, int count, void *stream)
         sth_problem *p = probs[b];
         for (int n = p->k + 1; n <= p->N; ++n) p->have_end[n] = 1;
         p->swept = true;
+    }
+    return STH_OK;
+}
+
+int sth_fine_sweep_chunk(sth_problem *const *probs, int count, long long max_steps, int *done_out, void *stream)
+{
+    if (count < 0 || (count > 0 && !probs)) return fail(STH_EINVAL, "bad batch");
+    if (max_steps < 1) return fail(STH_EINVAL, "max_steps must be >= 1");
+    hipStream_t st = (hipStream_t)stream;
+    for (int b = 0; b < count; ++b) {
+        if (!probs[b]) return fail(STH_EINVAL, "null problem in batch");
+        if (!probs[b]->coarse_done) return fail(STH_ESTATE, "sth_coarse_sweep must precede the fine sweep");
+        for (int c = 0; c < b; ++c)
+            if (probs[c] == probs[b]) return fail(STH_EINVAL, "a problem appears twice in the batch");
+    }
+    std::vector<SweepItem> items;
+    for (int b = 0; b < count; ++b) {
+        sth_problem *p = probs[b];
+        if (done_out) done_out[b] = p->swept ? 1 : 0;
+        if (p->k >= p->N || p->swept) continue;
+        if (p->chunk_pos < 0) {
+            // a new sweep: slice starts prepared now, units kept for the chunks
+            std::vector<SweepItem> mine;
+            std::vector<LiftJob> lifts;
+            std::vector<CopyJob> copies;
+            plan_problem_sweep(p, p->k, p->have_end, nullptr, mine, lifts, copies);
+            for (const CopyJob &c : copies)
+                HIPCHK(hipMemcpyAsync(c.dst, c.src, c.n * sizeof(uint4), hipMemcpyDeviceToDevice, st));
+            if (!lifts.empty()) {
+                LiftJob *dl = p->at<LiftJob>(p->L.lifts);
+                HIPCHK(hipMemcpyAsync(dl, lifts.data(), sizeof(LiftJob) * lifts.size(), hipMemcpyHostToDevice, st));
+                HIPCHK(launch_lift(p->prec, dl, (int)lifts.size(), p->nx, st));
+            }
+            p->chunk_units.clear();
+            for (const SweepItem &it : mine) p->chunk_units.push_back(it.unit);
+            p->chunk_pos = 0;
+        }
+        const long long s0 = p->chunk_pos, s1 = std::min(p->ns, s0 + max_steps);
+        const FineShape sh = class_shape(p->prec, p->nx, p->nv);
+        for (FineUnit u : p->chunk_units) {
+            u.step0 = s0;
+            u.step1 = s1;
+            items.push_back({sh, u, (double)(s1 - s0) * p->nx * p->nv});
+        }
+    }
+    sort_items(items);
+    if (!items.empty()) {
+        int slot = 0;
+        int rc = acquire_table(sizeof(FineUnit) * items.size(), &slot);
+        if (rc) return rc;
+        FineUnit *dtab = (FineUnit *)g_pool[slot].ptr;
+        std::vector<FineUnit> host(items.size());
+        for (size_t t = 0; t < items.size(); ++t) host[t] = items[t].unit;
+        HIPCHK(hipMemcpyAsync(dtab, host.data(), sizeof(FineUnit) * host.size(), hipMemcpyHostToDevice, st));
+        rc = issue_classes(items, dtab, st);
+        if (rc) return rc;
+        HIPCHK(hipEventRecord(g_pool[slot].ev, st));
+        g_pool[slot].used = true;
+    }
+    for (int b = 0; b < count; ++b) {
+        sth_problem *p = probs[b];
+        if (p->k >= p->N || p->swept || p->chunk_pos < 0) continue;
+        p->chunk_pos = std::min(p->ns, p->chunk_pos + max_steps);
+        if (p->chunk_pos >= p->ns) {
+            for (int n = p->k + 1; n <= p->N; ++n) p->have_end[n] = 1;
+            p->swept = true;
+            p->chunk_pos = -1;
+            p->chunk_units.clear();
+            if (done_out) done_out[b] = 1;
+        }
     }
     return STH_OK;
 }
@@ -1011,6 +1088,7 @@ int sth_graph_wait(sth_graph *g, void *stream, int *iters_out, double *last_err_
         p->last_err = e;
         p->coarse_done = true;
         p->swept = false;
+        p->chunk_pos = -1;
         std::fill(p->have_end.begin(), p->have_end.end(), 0);
         if (k > 0)
             for (int n = 1; n <= p->N; ++n) p->have_end[n] = 1;

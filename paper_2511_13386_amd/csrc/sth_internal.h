@@ -59,7 +59,18 @@ struct FineUnit {
     long long nsteps;         // steps of this unit (<= 0: pc->nsteps)
     const int *stop;          // the problem's stop flag (the unit does nothing
                               // when it is set), or NULL
+    // Step range [step0, step1) of the slice run by this launch (step1 <= 0:
+    // to the end).  step0 > 0 resumes from the checkpoint and the slot;
+    // step1 < nsteps stops after step1 - 1 and leaves the checkpoint and the
+    // slot (rows in w form, lazy projection and halos of the next parity)
+    // instead of the outputs.
+    long long step0, step1;
+    double *ckpt;             // [kCkptArrays][nx] when the slice is chunked
 };
+// Checkpoint of a suspended unit: rho, its compensation, Phi, m2 J, the
+// norms, the cell status of the last step and the criterion bits, each nx
+// doubles.
+constexpr int kCkptArrays = 7;
 
 // Launch shape of a fine-sweep kernel class.
 struct FineShape {

@@ -547,6 +547,9 @@ __global__ void __launch_bounds__(BLK) k_fine(const FineUnit *__restrict__ units
     const bool hybrid = flags & STH_HYBRID, field = flags & STH_FIELD, literal = flags & STH_LITERAL_R;
     const bool cellwise = hybrid && (flags & STH_LITERAL_FLUX);
     const long long nsteps = U.nsteps > 0 ? U.nsteps : C->nsteps;
+    const long long step0 = U.step0 > 0 ? U.step0 : 0;
+    const long long step1 = (U.step1 > 0 && U.step1 < nsteps) ? U.step1 : nsteps;
+    const bool resume = step0 > 0, suspend = step1 < nsteps;
     const double *__restrict__ g_e = C->e_p;
     const double *__restrict__ g_a = C->a_p;
     const double *__restrict__ g_eps = C->eps_p;
@@ -627,6 +630,7 @@ __global__ void __launch_bounds__(BLK) k_fine(const FineUnit *__restrict__ units
 #pragma unroll
             for (int j = 0; j < NV; ++j) Wr[k][j] = Real(0);
         }
+        if (resume) continue;
         if (k < ipt && i < nseg * kWave) {
             const bool valid = i < nx;
             const int seg = i / kWave, last = min(kWave - 1, nx - 1 - seg * kWave);
@@ -675,7 +679,65 @@ __global__ void __launch_bounds__(BLK) k_fine(const FineUnit *__restrict__ units
             }
         }
     }
+    // Resumed slice: the macroscopic state from the checkpoint, the rows,
+    // lazy projection and halos of this step's parity from the slot (the
+    // resident form reloads them into registers and LDS).
+    const int par0 = (int)(step0 & 1);
+    if (resume) {
+        const double *ck = U.ckpt;
+#pragma unroll
+        for (int k = 0; k < IPTM; ++k) {
+            const int i = k * BS + tid;
+            if (k >= ipt) continue;
+            if (i < nx) {
+                comp[k] = ck[(size_t)nx + i];
+                put_rho(i, ck[i]);
+                const double ph = ck[2 * (size_t)nx + i], pj = ck[3 * (size_t)nx + i];
+                s_phi[i] = ph;
+                *(i == nx - 1 ? s_phi - 1 : s_sink + lane) = ph;
+                s_phiJ[i] = pj;
+                *(i == nx - 1 ? s_phiJ - 1 : s_sink + lane) = pj;
+                put_nrm(i, (Real)ck[4 * (size_t)nx + i]);
+                const unsigned char cmo = (unsigned char)(ck[5 * (size_t)nx + i] != 0.0);
+                const unsigned char cr = (unsigned char)(ck[6 * (size_t)nx + i] != 0.0);
+                s_cm[(par0 ^ 1) * ncm + i] = cmo;
+                if (i == 0) s_cm[(par0 ^ 1) * ncm + nx] = cmo;
+                s_crit[i] = cr;
+                if (i == 0) s_crit[nx] = cr;
+            }
+            if constexpr (RES) {
+                if (i < nseg * kWave) {
+                    const bool valid = i < nx;
+                    const int seg = i / kWave, last = min(kWave - 1, nx - 1 - seg * kWave);
+#pragma unroll
+                    for (int j = 0; j < NV; ++j) Wr[k][j] = valid ? W[(size_t)j * ld + i] : Real(0);
+                    if (valid) s_c1[par0 * nx + i] = C1[(size_t)par0 * ld + i];
+                    if (lane == 0) {
+#pragma unroll 1
+                        for (int j = 0; j < HV; ++j) s_halo[HALO(par0, 0, seg) + j] = H[HALO(par0, 0, seg) + j];
+                    }
+                    if (lane == last) {
+#pragma unroll 1
+                        for (int j = 0; j < HV; ++j) s_halo[HALO(par0, 1, seg) + j] = H[HALO(par0, 1, seg) + j];
+                    }
+                }
+            }
+        }
+    }
     __syncthreads();
+    if (resume && hybrid) {
+        // status of the last step run: cells from the checkpoint, interface
+        // i kinetic iff one of its cells is
+#pragma unroll
+        for (int k = 0; k < IPTM; ++k) {
+            const int i = k * BS + tid;
+            if (k < ipt && i < nx) {
+                const unsigned ci = s_cm[(par0 ^ 1) * ncm + i], cn = s_cm[(par0 ^ 1) * ncm + i + 1];
+                cmbits = (cmbits & ~(1u << k)) | (ci << k);
+                kinbits = (kinbits & ~(1u << k)) | ((ci | cn) << k);
+            }
+        }
+    }
 
     double incl[IPTM];
 
@@ -850,7 +912,7 @@ __global__ void __launch_bounds__(BLK) k_fine(const FineUnit *__restrict__ units
         }
     };
 
-    if (hybrid) {
+    if (hybrid && !resume) {
         // criterion bits of the initial density (the norms are those of g_in)
         macro_scan();
         __syncthreads();
@@ -861,7 +923,7 @@ __global__ void __launch_bounds__(BLK) k_fine(const FineUnit *__restrict__ units
     }
 
     // ---------------------------------------------------------- step loop
-    for (long long n = 0; n < nsteps; ++n) {
+    for (long long n = step0; n < step1; ++n) {
         const int par = (int)(n & 1), npar = par ^ 1;
         tid = opaque_v(tid);
         lane = tid & (kWave - 1);
@@ -975,21 +1037,41 @@ __global__ void __launch_bounds__(BLK) k_fine(const FineUnit *__restrict__ units
     }
 
     // ---------------------------------------------------------- epilogue
-    const int fpar = (int)(nsteps & 1);
+    // End of the slice: status and density of the last step, outputs, rows
+    // reconstructed (g = w + M c1).  Suspended slice (step1 < nsteps): the
+    // checkpoint of the macroscopic state instead; the resident form also
+    // stores its rows (w form), lazy projection and halos of the next step's
+    // parity (the streamed form keeps them in the slot).
+    const int fpar = (int)(step1 & 1);
     const unsigned cm_last = cmbits;
-    if (hybrid) status(fpar);
-    if (nsteps > 0) density_update(cm_last);
+    if (!suspend) {
+        if (hybrid) status(fpar);
+        if (nsteps > 0) density_update(cm_last);
+    }
+    double *ck = U.ckpt;
 #pragma unroll
     for (int k = 0; k < IPTM; ++k) {
         const int i = k * BS + tid;
         if (k < ipt && i < nx) {
-            U.rho_out[i] = s_rho[i];
-            if (U.mask_out) U.mask_out[i] = hybrid ? (int)((cmbits >> k) & 1u) : 1;
+            if (suspend) {
+                ck[i] = s_rho[i];
+                ck[(size_t)nx + i] = comp[k];
+                ck[2 * (size_t)nx + i] = s_phi[i];
+                ck[3 * (size_t)nx + i] = s_phiJ[i];
+                ck[4 * (size_t)nx + i] = (double)s_nrm[i];
+                ck[5 * (size_t)nx + i] = (double)s_cm[(fpar ^ 1) * ncm + i];
+                ck[6 * (size_t)nx + i] = (double)s_crit[i];
+            } else {
+                U.rho_out[i] = s_rho[i];
+                if (U.mask_out) U.mask_out[i] = hybrid ? (int)((cmbits >> k) & 1u) : 1;
+            }
             if constexpr (RES) {
                 const Real c1 = s_c1[fpar * nx + i];
+                const Real cf = suspend ? Real(0) : c1;
 #pragma unroll
-                for (int j = 0; j < NV; ++j) W[(size_t)j * ld + i] = Wr[k][j] + vtr[4 * j + 1] * c1;
-            } else {
+                for (int j = 0; j < NV; ++j) W[(size_t)j * ld + i] = Wr[k][j] + vtr[4 * j + 1] * cf;
+                if (suspend) C1[(size_t)fpar * ld + i] = c1;
+            } else if (!suspend) {
                 const Real c1 = C1[(size_t)fpar * ld + i];
                 if (c1 != Real(0)) {
 #pragma unroll 1
@@ -997,6 +1079,25 @@ __global__ void __launch_bounds__(BLK) k_fine(const FineUnit *__restrict__ units
                 }
                 C1[i] = Real(0);
                 C1[ld + i] = Real(0);
+            }
+        }
+    }
+    if constexpr (RES) {
+        if (suspend) {
+#pragma unroll 1
+            for (int k = 0; k < ipt; ++k) {
+                const int i = k * BS + tid;
+                if (i < nseg * kWave) {
+                    const int seg = i / kWave, last = min(kWave - 1, nx - 1 - seg * kWave);
+                    if (lane == 0) {
+#pragma unroll 1
+                        for (int j = 0; j < HV; ++j) H[HALO(fpar, 0, seg) + j] = s_halo[HALO(fpar, 0, seg) + j];
+                    }
+                    if (lane == last) {
+#pragma unroll 1
+                        for (int j = 0; j < HV; ++j) H[HALO(fpar, 1, seg) + j] = s_halo[HALO(fpar, 1, seg) + j];
+                    }
+                }
             }
         }
     }

@@ -8,11 +8,16 @@ The server
   and an active slot is free (no device allocation per request: blocks are
   carved first-fit from one torch tensor);
 * keeps every admitted solve's state resident on the device;
-* advances all active solves together: one tick is one parareal iteration of
-  each of them, i.e. one batched fine sweep over every unconverged slice of
-  every active solve (`sth_fine_sweep_batched`, all kernel classes
-  concurrent) followed by their corrections in one launch
-  (`sth_parareal_correct_batched`, one read-back of all errors);
+* advances all active solves together, one tick at a time.  With
+  `chunk_steps` unset a tick is one parareal iteration of each of them: one
+  batched fine sweep over every unconverged slice of every active solve
+  (`sth_fine_sweep_batched`, all kernel classes concurrent) followed by their
+  corrections in one launch (`sth_parareal_correct_batched`, one read-back of
+  all errors).  With `chunk_steps = S` a tick advances every active sweep by
+  at most S fine steps per slice (`sth_fine_sweep_chunk`), and only the
+  solves whose sweep ended get their correction: a tick then lasts about S
+  steps of the slowest active class instead of a whole slice, so short solves
+  are not held behind long ones and arrivals join sooner;
 * retires a solve when it reaches its tolerance or its iteration limit,
   returns the slice-end densities and frees its block, which admits the next
   waiting requests at the next tick.
@@ -125,11 +130,13 @@ class _Active:
 
 
 class Server:
-    def __init__(self, budget_bytes: int, max_active: int = 512, stream=None):
+    def __init__(self, budget_bytes: int, max_active: int = 512, stream=None,
+                 chunk_steps: Optional[int] = None):
         import torch
         self.arena = ArenaAllocator(budget_bytes)
         self.max_active = max_active
         self.stream = stream if stream is not None else torch.cuda.Stream()
+        self.chunk_steps = chunk_steps
         self.ticks = 0
 
     def _admit(self, req: Request, now: float) -> Optional[_Active]:
@@ -168,18 +175,25 @@ class Server:
                 if k < len(pending):  # idle until the next arrival
                     time.sleep(max(0.0, pending[k].arrival - (clock() - t0)))
                 continue
-            # one tick: one parareal iteration of every active solve
-            sth.sth_fine_sweep_batched([a.prob for a in active], self.stream)
-            errs = sth.sth_parareal_correct_batched([a.prob for a in active], want_err=True,
-                                                    stream=self.stream)
-            for a, e in zip(active, errs):
-                a.errors.append(e)
+            # one tick: a parareal iteration of every active solve, or a
+            # chunk of fine steps of every active sweep
+            if self.chunk_steps is None:
+                ready = list(active)
+                sth.sth_fine_sweep_batched([a.prob for a in active], self.stream)
+            else:
+                done = sth.sth_fine_sweep_chunk([a.prob for a in active], self.chunk_steps, self.stream)
+                ready = [a for a, d in zip(active, done) if d]
+            if ready:
+                errs = sth.sth_parareal_correct_batched([a.prob for a in ready], want_err=True,
+                                                        stream=self.stream)
+                for a, e in zip(ready, errs):
+                    a.errors.append(e)
             self.ticks += 1
             done_t = clock() - t0
             still: List[_Active] = []
             for a in active:
                 it = len(a.errors)
-                if it >= a.req.max_iters or it >= a.prob.N or a.errors[-1] < a.req.tol:
+                if it and (it >= a.req.max_iters or it >= a.prob.N or a.errors[-1] < a.req.tol):
                     info = a.prob.info()
                     results[a.req.rid] = Result(a.req.rid, sth.sth_get_rho(a.prob), list(a.errors),
                                                 a.req.arrival, a.admitted, done_t,

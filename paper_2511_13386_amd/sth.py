@@ -31,7 +31,7 @@ EXPORTS = (
     "sth_fine_run", "sth_destroy", "sth_last_error", "sth_parareal_correct_batched", "sth_get_errors",
     "sth_graph_create", "sth_graph_launch", "sth_graph_wait", "sth_graph_destroy",
     "sth_fine_config_candidates", "sth_set_fine_config", "sth_get_fine_config",
-    "sth_coarse_sweep_batched",
+    "sth_coarse_sweep_batched", "sth_fine_sweep_chunk",
 )
 
 
@@ -98,6 +98,8 @@ def lib() -> ctypes.CDLL:
         L.sth_coarse_sweep.argtypes = [_VP, _VP]
         L.sth_fine_sweep_batched.argtypes = [ctypes.POINTER(_VP), ctypes.c_int, _VP]
         L.sth_coarse_sweep_batched.argtypes = [ctypes.POINTER(_VP), ctypes.c_int, _VP]
+        L.sth_fine_sweep_chunk.argtypes = [ctypes.POINTER(_VP), ctypes.c_int, ctypes.c_longlong,
+                                           ctypes.POINTER(ctypes.c_int), _VP]
         L.sth_parareal_correct.argtypes = [_VP, _D, ctypes.POINTER(ctypes.c_int), _VP]
         L.sth_moments_criteria.argtypes = [_VP, ctypes.c_int, _D, _D, _D, _D, _D,
                                            ctypes.POINTER(ctypes.c_int), _VP]
@@ -237,6 +239,16 @@ def sth_coarse_sweep_batched(problems: Sequence[Problem], stream=None) -> None:
 def sth_fine_sweep_batched(problems: Sequence[Problem], stream=None) -> None:
     arr = (_VP * len(problems))(*[q.h for q in problems])
     _check(lib().sth_fine_sweep_batched(arr, len(problems), _stream(stream)))
+
+
+def sth_fine_sweep_chunk(problems: Sequence[Problem], max_steps: int, stream=None) -> list:
+    """Advance the fine sweeps by at most max_steps steps per slice; returns,
+    per problem, whether its sweep has ended (and awaits its correction)."""
+    n = len(problems)
+    arr = (_VP * n)(*[q.h for q in problems])
+    done = (ctypes.c_int * max(n, 1))()
+    _check(lib().sth_fine_sweep_chunk(arr, n, int(max_steps), done, _stream(stream)))
+    return [bool(done[i]) for i in range(n)]
 
 
 def sth_parareal_correct(p: Problem, want_err: bool = True, stream=None):

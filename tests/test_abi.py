@@ -42,12 +42,13 @@ def _slot_elems(nx, nv):
 def test_footprint_of_the_configs():
     d2 = desc_of(wl.config2())
     b2 = sth.sth_footprint_bytes(d2)
-    # two (N+1)-slice state buffers dominate
-    s2 = 2 * 65 * _slot_elems(512, 64) * 8
+    # two (N+1)-slice state buffers dominate, then the (N+1) checkpoints of
+    # chunked sweeps (7 arrays of nx doubles each)
+    s2 = 2 * 65 * _slot_elems(512, 64) * 8 + 65 * 7 * 512 * 8
     assert s2 < b2 < s2 + (2 << 20)
     d3 = desc_of(wl.config3(), precision=sth.FP32_BULK)
     b3 = sth.sth_footprint_bytes(d3)
-    s3 = 2 * 129 * _slot_elems(2048, 128) * 4
+    s3 = 2 * 129 * _slot_elems(2048, 128) * 4 + 129 * 7 * 2048 * 8
     assert s3 < b3 < s3 + (10 << 20)
 
 

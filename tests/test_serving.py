@@ -38,7 +38,8 @@ def test_free_list_admission_order_under_pressure():
 
 
 @pytest.mark.gpu
-def test_served_results_equal_solves_alone():
+@pytest.mark.parametrize("chunk", [None, 97])
+def test_served_results_equal_solves_alone(chunk):
     """Six requests of different sizes and precisions arrive staggered and
     overlap on the device (an arena small enough that some must wait for
     memory); each served result equals its solve alone."""
@@ -54,7 +55,7 @@ def test_served_results_equal_solves_alone():
     descs = [desc_of(i, precision=p, K=2) for i, p in insts]
     sizes = [sth.sth_footprint_bytes(d) for d in descs]
     budget = sum(sorted(sizes)[-3:]) + 4096  # not all fit at once
-    srv = serving.Server(budget)
+    srv = serving.Server(budget, chunk_steps=chunk)
     reqs = [serving.Request(r, d, 0.002 * r, max_iters=2) for r, d in enumerate(descs)]
     res = srv.run(reqs)
     assert srv.ticks >= 3

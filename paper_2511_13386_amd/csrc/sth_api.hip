@@ -44,7 +44,7 @@ size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 // Device layout of one problem (offsets from the arena base).
 struct Layout {
     size_t cst, eps_p, eps_c, e_p, a_p, vtab, vrow64, vrow32, U, Gc, Fv, err, errh, ctl, work, kin, mask, g0, gend,
-        gst, ckpt, units, lifts, total;
+        gst, ckpt, units, total;
 };
 
 Layout layout(int nx, int nv, int N, int realsz)
@@ -74,7 +74,6 @@ Layout layout(int nx, int nv, int N, int realsz)
     L.gst = o;   o = al256(o + gsz * (size_t)(N + 1));
     L.ckpt = o;  o = al256(o + sizeof(double) * kCkptArrays * (size_t)nx * (size_t)(N + 1));
     L.units = o; o = al256(o + sizeof(FineUnit) * (size_t)(N + 1));
-    L.lifts = o; o = al256(o + sizeof(LiftJob) * (size_t)(N + 1));
     L.total = o;
     return L;
 }
@@ -101,13 +100,19 @@ int validate(const sth_problem_desc *d)
     return STH_OK;
 }
 
-// Pool of device tables for batched launches: a table is reused once the
-// event recorded after the launches that read it has completed.
+// Pool of tables for batched launches: a device table and its pinned host
+// mirror.  A table is staged in the mirror and copied asynchronously from
+// there (never from a caller's pageable buffer, which may be gone before the
+// copy runs); it is reserved from acquisition until release_table records
+// the event after the launches that read it, and reused once that event
+// has completed.
 struct TableSlot {
     void *ptr = nullptr;
+    void *host = nullptr;
     size_t cap = 0;
     hipEvent_t ev = nullptr;
-    bool used = false;
+    bool used = false;      // ev marks the last launches that read it
+    bool reserved = false;  // acquired, release_table not called yet
 };
 std::mutex g_pool_mu;
 std::vector<TableSlot> g_pool;
@@ -117,17 +122,51 @@ int acquire_table(size_t bytes, int *slot_out)
     std::lock_guard<std::mutex> lk(g_pool_mu);
     for (size_t s = 0; s < g_pool.size(); ++s) {
         TableSlot &t = g_pool[s];
-        if (t.cap < bytes) continue;
+        if (t.cap < bytes || t.reserved) continue;
         if (t.used && hipEventQuery(t.ev) != hipSuccess) continue;
+        t.reserved = true;
         *slot_out = (int)s;
         return STH_OK;
     }
     TableSlot t;
     t.cap = std::max(bytes, size_t(64) << 10);
     HIPCHK(hipMalloc(&t.ptr, t.cap));
+    HIPCHK(hipHostMalloc(&t.host, t.cap, hipHostMallocDefault));
     HIPCHK(hipEventCreateWithFlags(&t.ev, hipEventDisableTiming));
+    t.reserved = true;
     g_pool.push_back(t);
     *slot_out = (int)g_pool.size() - 1;
+    return STH_OK;
+}
+
+// Acquire a table, stage `bytes` of src in its mirror and copy it to the
+// device on st.  Returns the device table in *dptr.
+int put_table(const void *src, size_t bytes, hipStream_t st, int *slot_out, void **dptr)
+{
+    int slot = 0;
+    int rc = acquire_table(bytes, &slot);
+    if (rc) return rc;
+    void *dev = nullptr, *host = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        dev = g_pool[slot].ptr;
+        host = g_pool[slot].host;
+    }
+    if (bytes) std::memcpy(host, src, bytes);
+    HIPCHK(hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, st));
+    *slot_out = slot;
+    *dptr = dev;
+    return STH_OK;
+}
+
+// The launches that read the table have been issued on st.
+int release_table(int slot, hipStream_t st)
+{
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    TableSlot &t = g_pool[slot];
+    t.reserved = false;
+    HIPCHK(hipEventRecord(t.ev, st));
+    t.used = true;
     return STH_OK;
 }
 
@@ -487,6 +526,53 @@ int issue_classes(const std::vector<SweepItem> &items, FineUnit *dtab, hipStream
     return STH_OK;
 }
 
+// Lift jobs of a batch, one launch per problem, from one staged table.
+struct LiftBatch {
+    std::vector<LiftJob> jobs;
+    struct Run {
+        int prec, nx;
+        size_t begin, n;
+    };
+    std::vector<Run> runs;
+    void add(const sth_problem *p, const std::vector<LiftJob> &l)
+    {
+        if (l.empty()) return;
+        runs.push_back({p->prec, p->nx, jobs.size(), l.size()});
+        jobs.insert(jobs.end(), l.begin(), l.end());
+    }
+    int issue(hipStream_t st) const
+    {
+        if (jobs.empty()) return STH_OK;
+        int slot = 0;
+        void *tab = nullptr;
+        int rc = put_table(jobs.data(), sizeof(LiftJob) * jobs.size(), st, &slot, &tab);
+        if (rc) return rc;
+        hipError_t e = hipSuccess;
+        for (const Run &r : runs) {
+            if (e == hipSuccess) e = launch_lift(r.prec, (const LiftJob *)tab + r.begin, (int)r.n, r.nx, st);
+        }
+        rc = release_table(slot, st);
+        if (e != hipSuccess) return hip_fail(e, "launch_lift");
+        return rc;
+    }
+};
+
+// Sort the units into kernel classes, stage their table and launch them.
+int issue_units(std::vector<SweepItem> &items, hipStream_t st)
+{
+    if (items.empty()) return STH_OK;
+    sort_items(items);
+    std::vector<FineUnit> host(items.size());
+    for (size_t t = 0; t < items.size(); ++t) host[t] = items[t].unit;
+    int slot = 0;
+    void *tab = nullptr;
+    int rc = put_table(host.data(), sizeof(FineUnit) * host.size(), st, &slot, &tab);
+    if (rc) return rc;
+    const int rc2 = issue_classes(items, (FineUnit *)tab, st);
+    rc = release_table(slot, st);
+    return rc2 ? rc2 : rc;
+}
+
 CoarseJob coarse_job_of(sth_problem *p, int mode, int k)
 {
     CoarseJob j{};
@@ -672,9 +758,6 @@ int sth_coarse_sweep_batched(sth_problem *const *probs, int count, void *stream)
     }
     if (count == 0) return STH_OK;
     hipStream_t st = (hipStream_t)stream;
-    int slot = 0;
-    int rc = acquire_table(sizeof(CoarseJob) * (size_t)count, &slot);
-    if (rc) return rc;
     std::vector<CoarseJob> jobs(count);
     int block = kWave;
     size_t lds = 0;
@@ -687,11 +770,14 @@ int sth_coarse_sweep_batched(sth_problem *const *probs, int count, void *stream)
         block = std::max(block, bb);
         lds = std::max(lds, ll);
     }
-    CoarseJob *tab = (CoarseJob *)g_pool[slot].ptr;
-    HIPCHK(hipMemcpyAsync(tab, jobs.data(), sizeof(CoarseJob) * jobs.size(), hipMemcpyHostToDevice, st));
-    HIPCHK(launch_coarse_many(tab, count, block, lds, st));
-    HIPCHK(hipEventRecord(g_pool[slot].ev, st));
-    g_pool[slot].used = true;
+    int slot = 0;
+    void *tab = nullptr;
+    int rc = put_table(jobs.data(), sizeof(CoarseJob) * jobs.size(), st, &slot, &tab);
+    if (rc) return rc;
+    const hipError_t le = launch_coarse_many((const CoarseJob *)tab, count, block, lds, st);
+    rc = release_table(slot, st);
+    if (le != hipSuccess) return hip_fail(le, "launch_coarse_many");
+    if (rc) return rc;
     for (int b = 0; b < count; ++b) {
         sth_problem *p = probs[b];
         p->coarse_done = true;
@@ -713,6 +799,7 @@ int sth_fine_sweep_batched(sth_problem *const *probs, int count, void *stream)
         if (probs[b]->chunk_pos >= 0) return fail(STH_ESTATE, "a chunked fine sweep is in progress");
     }
     std::vector<SweepItem> items;
+    LiftBatch lb;
     for (int b = 0; b < count; ++b) {
         sth_problem *p = probs[b];
         if (p->k >= p->N) continue;
@@ -721,26 +808,12 @@ int sth_fine_sweep_batched(sth_problem *const *probs, int count, void *stream)
         plan_problem_sweep(p, p->k, p->have_end, nullptr, items, lifts, copies);
         for (const CopyJob &c : copies)
             HIPCHK(hipMemcpyAsync(c.dst, c.src, c.n * sizeof(uint4), hipMemcpyDeviceToDevice, st));
-        if (!lifts.empty()) {
-            LiftJob *dl = p->at<LiftJob>(p->L.lifts);
-            HIPCHK(hipMemcpyAsync(dl, lifts.data(), sizeof(LiftJob) * lifts.size(), hipMemcpyHostToDevice, st));
-            HIPCHK(launch_lift(p->prec, dl, (int)lifts.size(), p->nx, st));
-        }
+        lb.add(p, lifts);
     }
-    sort_items(items);
-    if (!items.empty()) {
-        int slot = 0;
-        int rc = acquire_table(sizeof(FineUnit) * items.size(), &slot);
-        if (rc) return rc;
-        FineUnit *dtab = (FineUnit *)g_pool[slot].ptr;
-        std::vector<FineUnit> host(items.size());
-        for (size_t t = 0; t < items.size(); ++t) host[t] = items[t].unit;
-        HIPCHK(hipMemcpyAsync(dtab, host.data(), sizeof(FineUnit) * host.size(), hipMemcpyHostToDevice, st));
-        rc = issue_classes(items, dtab, st);
-        if (rc) return rc;
-        HIPCHK(hipEventRecord(g_pool[slot].ev, st));
-        g_pool[slot].used = true;
-    }
+    int rc = lb.issue(st);
+    if (rc) return rc;
+    rc = issue_units(items, st);
+    if (rc) return rc;
     for (int b = 0; b < count; ++b) {
         sth_problem *p = probs[b];
         for (int n = p->k + 1; n <= p->N; ++n) p->have_end[n] = 1;
@@ -761,6 +834,7 @@ int sth_fine_sweep_chunk(sth_problem *const *probs, int count, long long max_ste
             if (probs[c] == probs[b]) return fail(STH_EINVAL, "a problem appears twice in the batch");
     }
     std::vector<SweepItem> items;
+    LiftBatch lb;
     for (int b = 0; b < count; ++b) {
         sth_problem *p = probs[b];
         if (done_out) done_out[b] = p->swept ? 1 : 0;
@@ -773,11 +847,7 @@ int sth_fine_sweep_chunk(sth_problem *const *probs, int count, long long max_ste
             plan_problem_sweep(p, p->k, p->have_end, nullptr, mine, lifts, copies);
             for (const CopyJob &c : copies)
                 HIPCHK(hipMemcpyAsync(c.dst, c.src, c.n * sizeof(uint4), hipMemcpyDeviceToDevice, st));
-            if (!lifts.empty()) {
-                LiftJob *dl = p->at<LiftJob>(p->L.lifts);
-                HIPCHK(hipMemcpyAsync(dl, lifts.data(), sizeof(LiftJob) * lifts.size(), hipMemcpyHostToDevice, st));
-                HIPCHK(launch_lift(p->prec, dl, (int)lifts.size(), p->nx, st));
-            }
+            lb.add(p, lifts);
             p->chunk_units.clear();
             for (const SweepItem &it : mine) p->chunk_units.push_back(it.unit);
             p->chunk_pos = 0;
@@ -790,20 +860,10 @@ int sth_fine_sweep_chunk(sth_problem *const *probs, int count, long long max_ste
             items.push_back({sh, u, (double)(s1 - s0) * p->nx * p->nv});
         }
     }
-    sort_items(items);
-    if (!items.empty()) {
-        int slot = 0;
-        int rc = acquire_table(sizeof(FineUnit) * items.size(), &slot);
-        if (rc) return rc;
-        FineUnit *dtab = (FineUnit *)g_pool[slot].ptr;
-        std::vector<FineUnit> host(items.size());
-        for (size_t t = 0; t < items.size(); ++t) host[t] = items[t].unit;
-        HIPCHK(hipMemcpyAsync(dtab, host.data(), sizeof(FineUnit) * host.size(), hipMemcpyHostToDevice, st));
-        rc = issue_classes(items, dtab, st);
-        if (rc) return rc;
-        HIPCHK(hipEventRecord(g_pool[slot].ev, st));
-        g_pool[slot].used = true;
-    }
+    int rc = lb.issue(st);
+    if (rc) return rc;
+    rc = issue_units(items, st);
+    if (rc) return rc;
     for (int b = 0; b < count; ++b) {
         sth_problem *p = probs[b];
         if (p->k >= p->N || p->swept || p->chunk_pos < 0) continue;
@@ -858,7 +918,12 @@ int sth_parareal_correct_batched(sth_problem *const *probs, int count, double *e
     int slot = 0;
     int rc = acquire_table(jbytes + sizeof(double) * (size_t)count, &slot);
     if (rc) return rc;
-    char *tab = (char *)g_pool[slot].ptr;
+    char *tab = nullptr, *htab = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        tab = (char *)g_pool[slot].ptr;
+        htab = (char *)g_pool[slot].host;
+    }
     double *derr = (double *)(tab + jbytes);
     std::vector<CoarseJob> jobs(count);
     int block = kWave;
@@ -873,13 +938,21 @@ int sth_parareal_correct_batched(sth_problem *const *probs, int count, double *e
         block = std::max(block, bb);
         lds = std::max(lds, ll);
     }
-    HIPCHK(hipMemcpyAsync(tab, jobs.data(), sizeof(CoarseJob) * jobs.size(), hipMemcpyHostToDevice, st));
-    HIPCHK(launch_coarse_many((const CoarseJob *)tab, count, block, lds, st));
+    std::memcpy(htab, jobs.data(), sizeof(CoarseJob) * jobs.size());
+    hipError_t e = hipMemcpyAsync(tab, htab, sizeof(CoarseJob) * jobs.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = launch_coarse_many((const CoarseJob *)tab, count, block, lds, st);
+    // errors back through the pinned mirror, past the jobs
+    double *herr = (double *)(htab + jbytes);
+    if (e == hipSuccess && errs_out)
+        e = hipMemcpyAsync(herr, derr, sizeof(double) * count, hipMemcpyDeviceToHost, st);
+    rc = release_table(slot, st);
+    if (e != hipSuccess) return hip_fail(e, "sth_parareal_correct_batched");
+    if (rc) return rc;
     std::vector<double> errs(count, 0.0);
-    if (errs_out) HIPCHK(hipMemcpyAsync(errs.data(), derr, sizeof(double) * count, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipEventRecord(g_pool[slot].ev, st));
-    g_pool[slot].used = true;
-    if (errs_out) HIPCHK(hipStreamSynchronize(st));
+    if (errs_out) {
+        HIPCHK(hipStreamSynchronize(st));
+        std::memcpy(errs.data(), herr, sizeof(double) * count);
+    }
     for (int b = 0; b < count; ++b) {
         sth_problem *p = probs[b];
         p->k += 1;

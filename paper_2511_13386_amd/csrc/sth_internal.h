@@ -62,7 +62,7 @@ struct FineUnit {
     // Step range [step0, step1) of the slice run by this launch (step1 <= 0:
     // to the end).  step0 > 0 resumes from the checkpoint and the slot;
     // step1 < nsteps stops after step1 - 1 and leaves the checkpoint and the
-    // slot (rows in w form, lazy projection and halos of the next parity)
+    // slot (rows in w form, lazy projection and halos of both parities)
     // instead of the outputs.
     long long step0, step1;
     double *ckpt;             // [kCkptArrays][nx] when the slice is chunked

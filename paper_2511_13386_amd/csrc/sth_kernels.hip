@@ -711,14 +711,22 @@ __global__ void __launch_bounds__(BLK) k_fine(const FineUnit *__restrict__ units
                     const int seg = i / kWave, last = min(kWave - 1, nx - 1 - seg * kWave);
 #pragma unroll
                     for (int j = 0; j < NV; ++j) Wr[k][j] = valid ? W[(size_t)j * ld + i] : Real(0);
-                    if (valid) s_c1[par0 * nx + i] = C1[(size_t)par0 * ld + i];
-                    if (lane == 0) {
-#pragma unroll 1
-                        for (int j = 0; j < HV; ++j) s_halo[HALO(par0, 0, seg) + j] = H[HALO(par0, 0, seg) + j];
+                    // both parities: a segment without kinetic interfaces
+                    // skips its pass and keeps the other parity's values
+                    if (valid) {
+                        s_c1[i] = C1[i];
+                        s_c1[nx + i] = C1[(size_t)ld + i];
                     }
-                    if (lane == last) {
 #pragma unroll 1
-                        for (int j = 0; j < HV; ++j) s_halo[HALO(par0, 1, seg) + j] = H[HALO(par0, 1, seg) + j];
+                    for (int pp = 0; pp < 2; ++pp) {
+                        if (lane == 0) {
+#pragma unroll 1
+                            for (int j = 0; j < HV; ++j) s_halo[HALO(pp, 0, seg) + j] = H[HALO(pp, 0, seg) + j];
+                        }
+                        if (lane == last) {
+#pragma unroll 1
+                            for (int j = 0; j < HV; ++j) s_halo[HALO(pp, 1, seg) + j] = H[HALO(pp, 1, seg) + j];
+                        }
                     }
                 }
             }
@@ -1040,8 +1048,10 @@ __global__ void __launch_bounds__(BLK) k_fine(const FineUnit *__restrict__ units
     // End of the slice: status and density of the last step, outputs, rows
     // reconstructed (g = w + M c1).  Suspended slice (step1 < nsteps): the
     // checkpoint of the macroscopic state instead; the resident form also
-    // stores its rows (w form), lazy projection and halos of the next step's
-    // parity (the streamed form keeps them in the slot).
+    // stores its rows (w form), and its lazy projection and halos of both
+    // parities (a segment without kinetic interfaces skips its pass and keeps
+    // the values of the other parity); the streamed form keeps all of them
+    // in the slot.
     const int fpar = (int)(step1 & 1);
     const unsigned cm_last = cmbits;
     if (!suspend) {
@@ -1070,7 +1080,10 @@ __global__ void __launch_bounds__(BLK) k_fine(const FineUnit *__restrict__ units
                 const Real cf = suspend ? Real(0) : c1;
 #pragma unroll
                 for (int j = 0; j < NV; ++j) W[(size_t)j * ld + i] = Wr[k][j] + vtr[4 * j + 1] * cf;
-                if (suspend) C1[(size_t)fpar * ld + i] = c1;
+                if (suspend) {
+                    C1[i] = s_c1[i];
+                    C1[(size_t)ld + i] = s_c1[nx + i];
+                }
             } else if (!suspend) {
                 const Real c1 = C1[(size_t)fpar * ld + i];
                 if (c1 != Real(0)) {
@@ -1089,13 +1102,16 @@ __global__ void __launch_bounds__(BLK) k_fine(const FineUnit *__restrict__ units
                 const int i = k * BS + tid;
                 if (i < nseg * kWave) {
                     const int seg = i / kWave, last = min(kWave - 1, nx - 1 - seg * kWave);
-                    if (lane == 0) {
 #pragma unroll 1
-                        for (int j = 0; j < HV; ++j) H[HALO(fpar, 0, seg) + j] = s_halo[HALO(fpar, 0, seg) + j];
-                    }
-                    if (lane == last) {
+                    for (int pp = 0; pp < 2; ++pp) {
+                        if (lane == 0) {
 #pragma unroll 1
-                        for (int j = 0; j < HV; ++j) H[HALO(fpar, 1, seg) + j] = s_halo[HALO(fpar, 1, seg) + j];
+                            for (int j = 0; j < HV; ++j) H[HALO(pp, 0, seg) + j] = s_halo[HALO(pp, 0, seg) + j];
+                        }
+                        if (lane == last) {
+#pragma unroll 1
+                            for (int j = 0; j < HV; ++j) H[HALO(pp, 1, seg) + j] = s_halo[HALO(pp, 1, seg) + j];
+                        }
                     }
                 }
             }

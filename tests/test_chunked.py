@@ -23,6 +23,10 @@ CASES = [
     (1100, 64, sth.FP32_BULK, False, 0, 37),   # streamed, wide workgroup, two slabs
     (1100, 16, sth.FP64, True, 0, 50),         # resident, three slabs
     (96, 32, sth.FP64, True, sth.LITERAL_FLUX, 13),
+    # many short chunks in a row: the unit tables of successive calls must
+    # not share host staging memory
+    (512, 128, sth.FP32_BULK, True, 0, 10),
+    (1024, 32, sth.FP32_BULK, True, 0, 16),
 ]
 
 
@@ -59,6 +63,32 @@ def test_chunked_sweep_equals_whole_sweep(nx, nv, prec, hybrid, flags, chunk):
         assert np.isfinite(e1) and e1 == e2
         assert np.array_equal(sth.sth_get_rho(whole), sth.sth_get_rho(chunked))
     assert whole.info().kinetic_iface_steps == chunked.info().kinetic_iface_steps
+    whole.close()
+    chunked.close()
+
+
+@pytest.mark.parametrize("r,chunk", [(7, 256), (47, 100), (61, 256)])
+def test_chunked_mostly_fluid_solves(r, chunk):
+    """Requests of the serving workload with small constant eps (most
+    segments fluid, so the resident form's pass skips them and their
+    other-parity halos and projections must survive a suspension) and
+    thousands of steps per slice: a chunked solve equals the whole-sweep
+    solve bit for bit."""
+    u = (wl.uniform_pm1(4242, 200)[r] + 1.0) * 0.5
+    inst = wl.random_instance(5000 + r, N=32, T=(0.1 + 0.9 * u) * 1e-2)
+    d = desc_of(inst, precision=sth.FP32_BULK, start_mode=sth.START_CARRY, K=2)
+    d.lift_order = 1
+    whole, chunked = sth.Problem(d), sth.Problem(d)
+    assert whole.info().fine_resident == 1 and whole.info().steps_per_slice > 4 * chunk
+    sth.parareal_solve(whole, K=2, fixed_iterations=True)
+    sth.sth_coarse_sweep(chunked)
+    for it in range(2):
+        while not sth.sth_fine_sweep_chunk([chunked], chunk)[0]:
+            pass
+        sth.sth_parareal_correct(chunked)
+    U = sth.sth_get_rho(chunked)
+    assert np.all(np.isfinite(U))
+    assert np.array_equal(U, sth.sth_get_rho(whole))
     whole.close()
     chunked.close()
 

@@ -468,6 +468,8 @@ def main():
             ev[k][1].record(stream)
         e, _ = sth.sth_parareal_correct(p, want_err=True, stream=stream)
         errs.append(e)
+        if k == 0:  # slice 1 after one iteration: one fine propagation from rho_in
+            first_slice = sth.sth_get_rho(p)[1]
         kin_now = p.info().kinetic_iface_steps
         kin_per_iter.append(kin_now - kin_prev)
         units_per_iter.append(inst.N - k)
@@ -573,6 +575,8 @@ def main():
             sth.sth_parareal_correct(q, want_err=False, stream=stream)
             b.synchronize()
             ms2.append(a.elapsed_time(b))
+            if k == 0:
+                first_slice2 = sth.sth_get_rho(q)[1]
         torch.cuda.synchronize()
         el2 = time.perf_counter() - t0
         info2 = q.info()
@@ -587,6 +591,8 @@ def main():
             "fine_step_us": float(np.mean(ms2)) * 1e3 / info2.steps_per_slice,
             "parareal_wall_s": el2,
             "max_rel_rho_diff": float(np.max(np.abs(U2 - U)) / np.max(np.abs(U))),
+            "first_slice_max_rel_rho_diff": float(np.max(np.abs(first_slice2 - first_slice))
+                                                  / np.max(np.abs(first_slice))),
             "mass_drift_rel": float(np.max(np.abs(U2.sum(axis=1) - m0)) / m0),
             "fine_form": "resident rows" if info2.fine_resident else "streamed rows",
         }

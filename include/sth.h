@@ -189,14 +189,17 @@ int  sth_fine_sweep_chunk(sth_problem *const *p, int count, long long max_steps,
  * U^{k+1}_{k+1} = F^{k+1}, U^n_{k+1} = G(U^{n-1}_{k+1}) + F^n - G(U^{n-1}_k)
  * for n > k+1, then k := k+1.  When err_out is non-NULL the call
  * synchronises and stores max_{n,i} |U^n_{k+1} - U^n_k|; k_out (optional)
- * receives the new k.  Returns STH_ESTATE if no fine sweep preceded it. */
+ * receives the new k.  Returns STH_ESTATE if no fine sweep preceded it,
+ * STH_ENONFINITE (after the correction, with *err_out set) when the error
+ * is not finite, i.e. a slice density holds a NaN or an infinity. */
 int  sth_parareal_correct(sth_problem *p, double *err_out, int *k_out, void *stream);
 
 /* The same correction for several problems in one launch (one workgroup per
  * problem), each problem at its own k.  When errs_out is non-NULL the call
- * synchronises once and stores each problem's error in errs_out[count].
- * Every problem must have had a fine sweep since its last correction, and
- * none may appear twice (STH_ESTATE / STH_EINVAL otherwise). */
+ * synchronises once and stores each problem's error in errs_out[count];
+ * STH_ENONFINITE (all corrections done, errs_out filled) when any of them is
+ * not finite.  Every problem must have had a fine sweep since its last
+ * correction, and none may appear twice (STH_ESTATE / STH_EINVAL otherwise). */
 int  sth_parareal_correct_batched(sth_problem *const *p, int count, double *errs_out, void *stream);
 
 /* Successive errors err_0 .. err_{k-1} of the iterations done so far
@@ -223,7 +226,8 @@ int  sth_graph_create(sth_problem *const *p, int count, sth_graph **out);
 int  sth_graph_launch(sth_graph *g, void *stream);
 /* Synchronise `stream`, then settle each problem's state from the device:
  * iterations done (iters_out[count], optional) and last error
- * (last_err_out[count], optional).  Afterwards the problems continue with
+ * (last_err_out[count], optional); STH_ENONFINITE (outputs filled) when a
+ * problem's last error is not finite.  Afterwards the problems continue with
  * the ordinary calls. */
 int  sth_graph_wait(sth_graph *g, void *stream, int *iters_out, double *last_err_out);
 void sth_graph_destroy(sth_graph *g);

@@ -367,7 +367,10 @@ double field_max(const std::vector<double> &rho, double rhobar, double dx)
     }
     m /= nx;
     double mx = 0.0;
-    for (int p = 0; p < nx; ++p) mx = std::max(mx, std::fabs(E[p] - m));
+    for (int p = 0; p < nx; ++p) {
+        const double a = std::fabs(E[p] - m);
+        mx = (a > mx || a != a) ? a : mx;  // a NaN propagates
+    }
     return mx;
 }
 
@@ -636,7 +639,20 @@ int sth_create(const sth_problem_desc *d, void *arena, size_t arena_bytes, sth_p
     const double Emax = (d->flags & STH_FIELD) ? field_max(rho0, p->rhobar, p->dx) : 0.0;
     const double dtmax = stable_dt(eps_p, p->dx, p->dv, d->vstar, p->m2, Emax, d->cfl_theta);
     p->dtG = d->T / N;
-    long long ns = d->steps_override > 0 ? d->steps_override : (long long)std::ceil(p->dtG / dtmax);
+    if (!std::isfinite(p->rhobar) || !std::isfinite(Emax)) {
+        delete p;
+        return fail(STH_ENONFINITE, "the mean density or its field overflows");
+    }
+    if (d->steps_override <= 0 && !(dtmax > 0.0 && std::isfinite(dtmax))) {
+        delete p;
+        return fail(STH_EINVAL, "no positive stable fine step for this data");
+    }
+    const double nsd = d->steps_override > 0 ? (double)d->steps_override : std::ceil(p->dtG / dtmax);
+    if (!(nsd <= 1e15)) {
+        delete p;
+        return fail(STH_EINVAL, "more than 1e15 fine steps per slice");
+    }
+    long long ns = (long long)nsd;
     if (ns < 1) ns = 1;
     p->ns = ns;
     p->dt = p->dtG / (double)ns;
@@ -897,6 +913,7 @@ int sth_parareal_correct(sth_problem *p, double *err_out, int *k_out, void *stre
         p->last_err = e;
     }
     if (k_out) *k_out = p->k;
+    if (err_out && !std::isfinite(*err_out)) return fail(STH_ENONFINITE, "non-finite density after the correction");
     return STH_OK;
 }
 
@@ -953,6 +970,7 @@ int sth_parareal_correct_batched(sth_problem *const *probs, int count, double *e
         HIPCHK(hipStreamSynchronize(st));
         std::memcpy(errs.data(), herr, sizeof(double) * count);
     }
+    bool finite = true;
     for (int b = 0; b < count; ++b) {
         sth_problem *p = probs[b];
         p->k += 1;
@@ -960,8 +978,10 @@ int sth_parareal_correct_batched(sth_problem *const *probs, int count, double *e
         if (errs_out) {
             errs_out[b] = errs[b];
             p->last_err = errs[b];
+            finite = finite && std::isfinite(errs[b]);
         }
     }
+    if (!finite) return fail(STH_ENONFINITE, "non-finite density after the correction (see errs_out)");
     return STH_OK;
 }
 
@@ -1150,6 +1170,7 @@ int sth_graph_wait(sth_graph *g, void *stream, int *iters_out, double *last_err_
     if (!g) return fail(STH_EINVAL, "null graph");
     if (!g->launched) return fail(STH_ESTATE, "the graph has not been launched");
     HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+    bool nonfinite = false;
     for (size_t b = 0; b < g->probs.size(); ++b) {
         sth_problem *p = g->probs[b];
         int ctl[2] = {0, 0};
@@ -1167,7 +1188,9 @@ int sth_graph_wait(sth_graph *g, void *stream, int *iters_out, double *last_err_
             for (int n = 1; n <= p->N; ++n) p->have_end[n] = 1;
         if (iters_out) iters_out[b] = k;
         if (last_err_out) last_err_out[b] = e;
+        if (k > 0 && !std::isfinite(e)) nonfinite = true;
     }
+    if (nonfinite) return fail(STH_ENONFINITE, "non-finite density in a recorded solve (see last_err_out)");
     return STH_OK;
 }
 

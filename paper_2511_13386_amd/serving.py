@@ -18,7 +18,8 @@ The server
   solves whose sweep ended get their correction: a tick then lasts about S
   steps of the slowest active class instead of a whole slice, so short solves
   are not held behind long ones and arrivals join sooner;
-* retires a solve when it reaches its tolerance or its iteration limit,
+* retires a solve when it reaches its tolerance or its iteration limit, or
+  as failed (`Result.ok` False) when a slice density turns non-finite,
   returns the slice-end densities and frees its block, which admits the next
   waiting requests at the next tick.
 
@@ -113,6 +114,7 @@ class Result:
     admitted: float
     finished: float
     cell_updates: float
+    ok: bool = True                 # False: a slice density went non-finite
 
     @property
     def latency(self) -> float:
@@ -185,7 +187,7 @@ class Server:
                 ready = [a for a, d in zip(active, done) if d]
             if ready:
                 errs = sth.sth_parareal_correct_batched([a.prob for a in ready], want_err=True,
-                                                        stream=self.stream)
+                                                        stream=self.stream, nonfinite_ok=True)
                 for a, e in zip(ready, errs):
                     a.errors.append(e)
             self.ticks += 1
@@ -193,11 +195,12 @@ class Server:
             still: List[_Active] = []
             for a in active:
                 it = len(a.errors)
-                if it and (it >= a.req.max_iters or it >= a.prob.N or a.errors[-1] < a.req.tol):
+                bad = bool(it) and not np.isfinite(a.errors[-1])
+                if it and (bad or it >= a.req.max_iters or it >= a.prob.N or a.errors[-1] < a.req.tol):
                     info = a.prob.info()
                     results[a.req.rid] = Result(a.req.rid, sth.sth_get_rho(a.prob), list(a.errors),
                                                 a.req.arrival, a.admitted, done_t,
-                                                info.kinetic_iface_steps * a.prob.nv)
+                                                info.kinetic_iface_steps * a.prob.nv, ok=not bad)
                     a.prob.close()
                     self.arena.release(a.off, a.size)
                 else:

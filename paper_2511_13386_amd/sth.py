@@ -259,12 +259,16 @@ def sth_parareal_correct(p: Problem, want_err: bool = True, stream=None):
     return (err.value if want_err else None), k.value
 
 
-def sth_parareal_correct_batched(problems: Sequence[Problem], want_err: bool = True, stream=None):
+def sth_parareal_correct_batched(problems: Sequence[Problem], want_err: bool = True, stream=None,
+                                 nonfinite_ok: bool = False):
     """Corrections of several problems in one launch; returns their errors
-    (None when want_err is False)."""
+    (None when want_err is False).  A non-finite error raises StHError
+    (STH_ENONFINITE) unless nonfinite_ok, which returns it in the list."""
     arr = (_VP * len(problems))(*[q.h for q in problems])
     errs = np.zeros(len(problems)) if want_err else None
-    _check(lib().sth_parareal_correct_batched(arr, len(problems), _d(errs), _stream(stream)))
+    rc = lib().sth_parareal_correct_batched(arr, len(problems), _d(errs), _stream(stream))
+    if not (nonfinite_ok and rc == STH_ENONFINITE):
+        _check(rc)
     return None if errs is None else errs.tolist()
 
 

@@ -97,3 +97,17 @@ def test_workload_generators_are_deterministic():
     s = wl.splitmix64(0, 3)
     # published first outputs of SplitMix64 with seed 0
     assert [int(v) for v in s] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+
+
+def test_data_without_a_stable_step_is_refused():
+    """A density whose field overflows the stable-step bound is refused at
+    creation (no device work), so no slice runs an unbounded step count."""
+    import ctypes
+    inst = wl.small_hybrid(seed=26, nx=64, nv=32, N=3)
+    for scale, code, word in ((1e300, sth.STH_EINVAL, "stable"), (1e308, sth.STH_ENONFINITE, "overflows")):
+        inst.rho_in = scale * (1.0 + 0.5 * np.cos(2 * np.pi * wl.cell_centres(64)))
+        c, keep = desc_of(inst).to_c()
+        h = ctypes.c_void_p()
+        rc = sth.lib().sth_create(ctypes.byref(c), None, 0, ctypes.byref(h))
+        assert rc == code and not h.value
+        assert word in sth.sth_last_error()

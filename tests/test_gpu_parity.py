@@ -416,3 +416,35 @@ def test_state_errors():
         sth.sth_parareal_correct(p)
     assert e.value.code == sth.STH_ESTATE
     p.close()
+
+
+def test_nonfinite_density_is_reported():
+    """Densities that overflow make the correction report STH_ENONFINITE
+    (after updating the state), in single, batched and recorded solves."""
+    inst = wl.small_hybrid(seed=24, nx=64, nv=32, N=3, T=2e-3, K=2)
+    # a start perturbation whose fluxes overflow: slice 1 turns non-finite
+    inst.g_in = 1e300 * np.sign(np.sin(np.arange(64 * 32) * 0.7)).reshape(64, 32)
+    p = sth.Problem(desc_of(inst, K=2))
+    sth.sth_coarse_sweep(p)
+    sth.sth_fine_sweep_batched([p])
+    with pytest.raises(sth.StHError) as ei:
+        sth.sth_parareal_correct(p)
+    assert ei.value.code == sth.STH_ENONFINITE
+    assert p.info().k_done == 1
+    q = sth.Problem(desc_of(wl.small_hybrid(seed=25, nx=64, nv=32, N=3, T=2e-3, K=2), K=2))
+    for r in (p, q):
+        sth.sth_coarse_sweep(r)
+    sth.sth_fine_sweep_batched([p, q])
+    with pytest.raises(sth.StHError):
+        sth.sth_parareal_correct_batched([p, q])
+    sth.sth_fine_sweep_batched([p, q])
+    errs = sth.sth_parareal_correct_batched([p, q], nonfinite_ok=True)
+    assert not np.isfinite(errs[0]) and np.isfinite(errs[1])
+    g = sth.Graph([p, q])
+    g.launch()
+    with pytest.raises(sth.StHError) as ei:
+        g.wait()
+    assert ei.value.code == sth.STH_ENONFINITE
+    g.close()
+    p.close()
+    q.close()

@@ -67,3 +67,26 @@ def test_served_results_equal_solves_alone(chunk):
         assert r.latency > 0 and r.finished >= r.admitted >= 0
         p.close()
     torch.cuda.synchronize()
+
+
+@pytest.mark.gpu
+def test_a_nonfinite_request_fails_alone():
+    """A request whose densities overflow is retired as failed after its
+    first correction; the requests served with it are unaffected."""
+    torch = pytest.importorskip("torch")
+    good = [desc_of(wl.small_hybrid(seed=21 + i, nx=96, nv=32, N=3, T=2e-3, K=2), K=2) for i in range(2)]
+    inst = wl.small_hybrid(seed=23, nx=64, nv=32, N=3, T=2e-3, K=2)
+    # a start perturbation whose fluxes overflow
+    inst.g_in = 1e300 * np.sign(np.sin(np.arange(64 * 32) * 0.7)).reshape(64, 32)
+    bad = desc_of(inst, K=2)
+    descs = [good[0], bad, good[1]]
+    srv = serving.Server(sum(sth.sth_footprint_bytes(d) for d in descs) + 4096, chunk_steps=64)
+    res = srv.run([serving.Request(r, d, 0.0, max_iters=2) for r, d in enumerate(descs)])
+    assert [r.ok for r in res] == [True, False, True]
+    assert len(res[1].errors) == 1 and not np.isfinite(res[1].errors[0])
+    for r, d in ((res[0], good[0]), (res[2], good[1])):
+        p = sth.Problem(d)
+        sth.parareal_solve(p, K=2, fixed_iterations=True)
+        assert np.array_equal(r.rho, sth.sth_get_rho(p))
+        p.close()
+    torch.cuda.synchronize()

@@ -86,7 +86,7 @@ def parse():
     ap.add_argument("--no-other-precision", action="store_true",
                     help="config2: skip the same solve in the other precision")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--workload", choices=["config2", "batch", "serve", "convergence"], default="config2",
+    ap.add_argument("--workload", choices=["config2", "batch", "serve", "convergence", "1d3v"], default="config2",
                     help="config2: the hybrid parareal problem the metric is quoted on; "
                          "batch: many independent instances in one batched sweep per iteration")
     ap.add_argument("--batch-count", type=int, default=256)
@@ -402,6 +402,51 @@ def run_convergence(args, torch, sth, wl):
     print(json.dumps(out), flush=True)
 
 
+def run_1d3v(args, torch, sth, wl):
+    """The paper's 1D3V setting (Nx = 32, Nv = 32 x 16 x 16, N_g = 200,
+    T_f = 1, tol 1e-10, eta0 = delta0 = 1e-5): parareal iterations and wall
+    clock against eps, with and without domain adaptation, for states of
+    the form g(x, vx) M(vy) M(vz) (the initial data of the study has it)."""
+    eps_list = [1.0, 1e-1, 1e-2, 1e-3, 1e-4]
+    rows = []
+    t0 = time.perf_counter()
+    for adapt in (False, True):
+        for eps in eps_list:
+            inst = wl.paper_setting(eps, adaptation=adapt, lift_order=1)
+            d = sth.Desc(nx=inst.nx, nv=inst.nv, eps_iface=inst.eps_iface, eps_cell=inst.eps_cell,
+                         rho0=inst.rho_in, T=inst.T, n_slices=inst.N, k_max=inst.N, tol=inst.tol,
+                         eta0=inst.eta0, delta0=inst.delta0, lift_order=1, start_mode=sth.START_LIFT,
+                         cfl_theta=inst.theta, flags=sth.FIELD | (sth.HYBRID if adapt else 0),
+                         Lx=inst.Lx, vstar=inst.vstar, nv_y=16, nv_z=16)
+            p = sth.Problem(d)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            errs = sth.parareal_solve(p, K=inst.N, tol=inst.tol)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t1
+            info = p.info()
+            cells = info.kinetic_iface_steps * inst.nv
+            rows.append({"adaptation": adapt, "eps": eps, "iterations": len(errs), "final_err": errs[-1],
+                         "parareal_wall_s": wall, "steps_per_slice": info.steps_per_slice,
+                         "kinetic_cell_updates_vx": cells,
+                         "kinetic_cell_updates_3d_equivalent": cells * 16 * 16,
+                         "norm_scale": info.norm_scale})
+            p.close()
+            print(f"# 1d3v eps={eps:g} adaptation={adapt}: {len(errs)} iterations, {wall:.2f} s",
+                  file=sys.stderr, flush=True)
+    for r in rows:
+        if r["adaptation"]:
+            off = [q for q in rows if not q["adaptation"] and q["eps"] == r["eps"]][0]
+            r["wall_ratio_full_kinetic_over_hybrid"] = off["parareal_wall_s"] / r["parareal_wall_s"]
+    out = {"metric": "1D3V parareal iterations and wall clock against eps (paper's Table 3 shape)",
+           "value": None, "unit": "s", "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": "Nx=32, Nv=32x16x16 (states g(x,vx)M(vy)M(vz), advanced through their vx "
+                                  "factor), x*=2pi, v*=8, N_g=200, T_f=1, tol 1e-10, eta0=delta0=1e-5, "
+                                  "rho_in=3(1+0.9cos x), g'=0, lifted slice starts (L=1), FP64"},
+           "runs": rows, "wall_s": time.perf_counter() - t0}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -424,6 +469,9 @@ def main():
         return
     if args.workload == "convergence":
         run_convergence(args, torch, sth, wl)
+        return
+    if args.workload == "1d3v":
+        run_1d3v(args, torch, sth, wl)
         return
     prec = sth.FP64 if args.precision == "fp64" else sth.FP32_BULK
     inst = wl.config2(seed=args.seed, nx=args.nx, nv=args.nv, N=args.slices, T=args.T,

@@ -97,6 +97,21 @@ typedef struct {
                                   STH_LITERAL_FLUX | STH_COARSE_EXPLICIT      */
     int           precision;   /* STH_FP64 or STH_FP32_BULK                    */
     long long     steps_override; /* > 0 forces the fine steps per slice       */
+    int           nv_y, nv_z;  /* 0, 0: 1D1V.  Otherwise the 1D3V problem of
+                                  the paper (velocity box [-vstar, vstar]^3,
+                                  nv x nv_y x nv_z midpoint nodes, field along
+                                  x) for states of the form
+                                  g(x, vx) M(vy) M(vz), M the discrete
+                                  normalised Maxwellian of each axis: the form
+                                  every state keeps when the initial one has
+                                  it, since transport, the field and the
+                                  relaxation act on vx only and the
+                                  projection integrates M(vy) M(vz) to 1.  The
+                                  solver carries g(x, vx) (g0 and the outputs
+                                  are that factor); the 3D norm of the
+                                  perturbation is sqrt(C) times its vx norm,
+                                  C = sum M(vy)^2 dvy * sum M(vz)^2 dvz.
+                                  Even, 2..512, both set or both 0.            */
 } sth_problem_desc;
 
 typedef struct {
@@ -116,6 +131,7 @@ typedef struct {
     int       fine_block;      /* threads per fine-sweep workgroup            */
     long long coarse_steps;    /* steps of the coarse scheme per interval:
                                   1, or that of STH_COARSE_EXPLICIT           */
+    double    norm_scale;      /* sqrt(C) of the 1D3V form, 1 in 1D1V         */
 } sth_info;
 
 /* Launch configuration of the fine kernel for one kernel class: the class

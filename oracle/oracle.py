@@ -47,6 +47,7 @@ class Params(ctypes.Structure):
         ("flags", ctypes.c_int), ("lift_order", ctypes.c_int),
         ("start_mode", ctypes.c_int),
         ("coarse_steps", ctypes.c_long),
+        ("norm_scale", ctypes.c_double),
     ]
 
 
@@ -269,8 +270,18 @@ def num_threads():
 
 
 # ----------------------------------------------------------------------------- problem set-up
+def axis_m2sum(n, vstar):
+    """sum_j M_j^2 dv of the discrete normalised Maxwellian on n midpoint
+    nodes of [-vstar, vstar] (a transverse velocity axis in 1D3V)."""
+    dv = 2.0 * vstar / n
+    v = -vstar + (np.arange(n) + 0.5) * dv
+    M = np.exp(-0.5 * v * v)
+    M = M / (np.sum(M) * dv)
+    return float(np.sum(M * M) * dv)
+
+
 def setup(nx, nv, eps_iface, rho_in, *, T, N, theta=1.0, Lx=1.0, vstar=8.0, eta0=1e-3,
-          delta0=1e-3, flags=FIELD, lift_order=3, start_mode=START_LIFT):
+          delta0=1e-3, flags=FIELD, lift_order=3, start_mode=START_LIFT, nv_y=0, nv_z=0):
     """Derive rhobar, the fine step and steps per slice the way the oracle
     defines them (mean initial density; stable step bound; equal steps per
     slice).  Returns (Params, steps_per_slice, dtG)."""
@@ -289,6 +300,8 @@ def setup(nx, nv, eps_iface, rho_in, *, T, N, theta=1.0, Lx=1.0, vstar=8.0, eta0
     # explicit coarse scheme: its diffusive stable step with the same margin
     m2 = velocity_grid(nv, vstar)[2]
     p.coarse_steps = int(math.ceil((T / N) / (theta * 0.75 * dx * dx / (2.0 * m2))))
+    if nv_y:
+        p.norm_scale = math.sqrt(axis_m2sum(nv_y, vstar) * axis_m2sum(nv_z, vstar))
     return p, ns, T / N
 
 

@@ -257,13 +257,16 @@ static double crit_R(const orc_params *p, double eps_c, double R)
     return (p->flags & ORC_LITERAL_R) ? fabs(R) : eps_c * eps_c * fabs(R);
 }
 
+/* N_p = eps_p ||g'_p||_2 over the velocity space; for 1D3V states of the
+ * form g(x, vx) M(vy) M(vz) the 3D norm is norm_scale times the vx norm. */
 static void gnorms(const orc_params *p, const double *eps_iface, const double *g, double *N)
 {
     double dv = 2.0 * p->vstar / p->nv;
+    double ns = p->norm_scale > 0.0 ? p->norm_scale : 1.0;
     for (int q = 0; q < p->nx; ++q) {
         double s = 0.0;
         for (int j = 0; j < p->nv; ++j) s += g[q * p->nv + j] * g[q * p->nv + j] * dv;
-        N[q] = eps_iface[q] * sqrt(s);
+        N[q] = (eps_iface[q] * ns) * sqrt(s);
     }
 }
 

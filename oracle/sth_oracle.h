@@ -59,6 +59,8 @@ typedef struct {
     int    lift_order;  /* L in {1,2,3} for the lifting operator              */
     int    start_mode;  /* ORC_START_* for the parareal slice starts          */
     long   coarse_steps; /* steps of S^0 per coarse interval (ORC_COARSE_EXPLICIT) */
+    double norm_scale;  /* 1D3V states g(x,vx) M(vy) M(vz): the 3D norm of the
+                           perturbation over its vx norm (<= 0 means 1, 1D1V) */
 } orc_params;
 
 typedef struct {

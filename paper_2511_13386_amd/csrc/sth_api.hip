@@ -43,7 +43,7 @@ size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Device layout of one problem (offsets from the arena base).
 struct Layout {
-    size_t cst, eps_p, eps_c, e_p, a_p, vtab, vrow64, vrow32, U, Gc, Fv, err, errh, ctl, work, kin, mask, g0, gend,
+    size_t cst, eps_p, eps_c, eps_n, e_p, a_p, vtab, vrow64, vrow32, U, Gc, Fv, err, errh, ctl, work, kin, mask, g0, gend,
         gst, ckpt, units, total;
 };
 
@@ -55,6 +55,7 @@ Layout layout(int nx, int nv, int N, int realsz)
     L.cst = o;   o = al256(o + sizeof(FineConst));
     L.eps_p = o; o = al256(o + sizeof(double) * nx);
     L.eps_c = o; o = al256(o + sizeof(double) * nx);
+    L.eps_n = o; o = al256(o + sizeof(double) * nx);
     L.e_p = o;   o = al256(o + sizeof(double) * nx);
     L.a_p = o;   o = al256(o + sizeof(double) * nx);
     L.vtab = o;  o = al256(o + sizeof(double) * 4 * nv);
@@ -97,6 +98,9 @@ int validate(const sth_problem_desc *d)
         return fail(STH_EINVAL, "unknown flags");
     if (fine_shape(d->precision == STH_FP64 ? 0 : 1, d->nx, d->nv, 0, 0).lds > kMaxLds)
         return fail(STH_EINVAL, "unit too large for one workgroup's LDS");
+    if ((d->nv_y == 0) != (d->nv_z == 0)) return fail(STH_EINVAL, "nv_y and nv_z must be both 0 or both set");
+    if (d->nv_y != 0 && (d->nv_y < 2 || d->nv_y > 512 || (d->nv_y & 1) || d->nv_z < 2 || d->nv_z > 512 || (d->nv_z & 1)))
+        return fail(STH_EINVAL, "nv_y and nv_z must be even, in [2, 512]");
     return STH_OK;
 }
 
@@ -272,6 +276,7 @@ struct sth_problem {
     int nx, nv, N, K, prec, realsz, flags, start_mode, lift_order;
     double Lx, vstar, T, tol, dx, dv, dt, dtG, m2, rhobar, eta0, delta0;
     long long ns, coarse_steps = 1;
+    double nscale = 1.0;    // 3D norm of a g(x, vx) M(vy) M(vz) state over its vx norm
     char *base = nullptr;
     size_t bytes = 0;
     bool owned = false;
@@ -334,6 +339,23 @@ void velocity_table(int nv, double vstar, double dx, std::vector<double> &vtab, 
         vtab[2 * nv + j] = v[j] * M[j];
         vtab[3 * nv + j] = v[j];
     }
+}
+
+// sum_j M_j^2 dv for the discrete normalised Maxwellian on n midpoint nodes
+// of [-vstar, vstar] (a transverse axis of the 1D3V velocity box).
+double axis_m2sum(int n, double vstar)
+{
+    const double dv = 2.0 * vstar / n;
+    std::vector<double> M(n);
+    double Z = 0.0;
+    for (int j = 0; j < n; ++j) {
+        const double v = -vstar + (j + 0.5) * dv;
+        M[j] = std::exp(-0.5 * v * v);
+        Z += M[j] * dv;
+    }
+    double s = 0.0;
+    for (int j = 0; j < n; ++j) s += (M[j] / Z) * (M[j] / Z) * dv;
+    return s;
 }
 
 // Stable fine step of the exponential-relaxation / upwind micro step:
@@ -631,6 +653,7 @@ int sth_create(const sth_problem_desc *d, void *arena, size_t arena_bytes, sth_p
     p->eta0 = d->eta0; p->delta0 = d->delta0;
     p->dx = d->Lx / nx;
     p->dv = 2.0 * d->vstar / nv;
+    p->nscale = d->nv_y ? std::sqrt(axis_m2sum(d->nv_y, d->vstar) * axis_m2sum(d->nv_z, d->vstar)) : 1.0;
     std::vector<double> vtab;
     velocity_table(nv, d->vstar, p->dx, vtab, p->m2);
     double s = 0.0;
@@ -696,6 +719,7 @@ int sth_create(const sth_problem_desc *d, void *arena, size_t arena_bytes, sth_p
     p->coarse_steps = c.coarse_steps;
     c.eps_p = p->at<double>(p->L.eps_p);
     c.eps_c = p->at<double>(p->L.eps_c);
+    c.eps_n = p->at<double>(p->L.eps_n);
     c.e_p = p->at<double>(p->L.e_p);
     c.a_p = p->at<double>(p->L.a_p);
     c.vtab = p->at<double>(p->L.vtab);
@@ -717,6 +741,11 @@ int sth_create(const sth_problem_desc *d, void *arena, size_t arena_bytes, sth_p
     if (e == hipSuccess) e = up(p->L.cst, &c, sizeof(c));
     if (e == hipSuccess) e = up(p->L.eps_p, eps_p.data(), sizeof(double) * nx);
     if (e == hipSuccess) e = up(p->L.eps_c, eps_c.data(), sizeof(double) * nx);
+    {
+        std::vector<double> eps_n(nx);
+        for (int i = 0; i < nx; ++i) eps_n[i] = eps_p[i] * p->nscale;
+        if (e == hipSuccess) e = up(p->L.eps_n, eps_n.data(), sizeof(double) * nx);
+    }
     if (e == hipSuccess) e = up(p->L.e_p, e_p.data(), sizeof(double) * nx);
     if (e == hipSuccess) e = up(p->L.a_p, a_p.data(), sizeof(double) * nx);
     if (e == hipSuccess) e = up(p->L.vtab, vtab.data(), sizeof(double) * 4 * nv);
@@ -1318,6 +1347,7 @@ int sth_get_info(const sth_problem *p, sth_info *out)
     out->fine_resident = sh.stream ? 0 : 1;
     out->fine_block = sh.block;
     out->coarse_steps = (p->flags & STH_COARSE_EXPLICIT) ? p->coarse_steps : 1;
+    out->norm_scale = p->nscale;
     return STH_OK;
 }
 

@@ -25,6 +25,7 @@ struct FineConst {
     long long coarse_steps; // steps of S^0 per coarse interval (STH_COARSE_EXPLICIT)
     const double *eps_p;  // [nx] eps at interfaces
     const double *eps_c;  // [nx] eps at cell centres
+    const double *eps_n;  // [nx] eps_p times the norm scale of the velocity space (norms only)
     const double *e_p;    // [nx] exp(-dt/eps_p^2)
     const double *a_p;    // [nx] -expm1(-dt/eps_p^2)
     const double *vtab;   // [4][nv]: |v_j|/dx, M_j, v_j M_j, v_j

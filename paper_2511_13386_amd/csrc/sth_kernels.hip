@@ -553,6 +553,7 @@ __global__ void __launch_bounds__(BLK) k_fine(const FineUnit *__restrict__ units
     const double *__restrict__ g_e = C->e_p;
     const double *__restrict__ g_a = C->a_p;
     const double *__restrict__ g_eps = C->eps_p;
+    const double *__restrict__ g_epsn = C->eps_n;  // norms: eps times the velocity-space scale
     const double *__restrict__ g_epsc = C->eps_c;
 
     const FineLds L = fine_lds(nx, NV, (int)sizeof(Real), nslot, RES);
@@ -673,7 +674,7 @@ __global__ void __launch_bounds__(BLK) k_fine(const FineUnit *__restrict__ units
             }
             if (valid) {
                 put_rho(i, U.rho_in[i]);
-                put_nrm(i, (Real)g_eps[i] * (Real)sqrt((double)(q * dvR)));
+                put_nrm(i, (Real)g_epsn[i] * (Real)sqrt((double)(q * dvR)));
                 s_cm[ncm + i] = 1;
                 if (i == 0) s_cm[ncm + nx] = 1;
             }
@@ -981,7 +982,7 @@ __global__ void __launch_bounds__(BLK) k_fine(const FineUnit *__restrict__ units
                     C1[(size_t)npar * ld + i] = c1n;
                 }
                 if (kv) Phi = -(o.phi * dx) * dv;
-                Nn = (Real)((double)epsr * sqrt(o.gg * dv));
+                Nn = (Real)(g_epsn[iv] * sqrt(o.gg * dv));
             }
             if (valid) {
                 s_phi[i] = Phi;
@@ -1742,7 +1743,7 @@ __global__ void __launch_bounds__(1024) k_diag(DiagJob J)
             }
         }
         oPhi[p] = -ph;
-        oN[p] = C->eps_p[p] * sqrt(q);
+        oN[p] = C->eps_n[p] * sqrt(q);
         const double ec = field ? 0.5 * (s_E[wrapi(p - 1, nx)] + s_E[p]) : 0.0;
         s_jc[p] = fd1(s_rho, p, nx) * inv_dx - ec * s_rho[p];
         part += s_jc[p];

@@ -54,6 +54,7 @@ class ProblemDesc(ctypes.Structure):
         ("lift_order", ctypes.c_int), ("start_mode", ctypes.c_int),
         ("cfl_theta", ctypes.c_double), ("flags", ctypes.c_int), ("precision", ctypes.c_int),
         ("steps_override", ctypes.c_longlong),
+        ("nv_y", ctypes.c_int), ("nv_z", ctypes.c_int),
     ]
 
 
@@ -66,6 +67,7 @@ class Info(ctypes.Structure):
         ("last_err", ctypes.c_double), ("footprint_bytes", ctypes.c_size_t),
         ("fine_resident", ctypes.c_int), ("fine_block", ctypes.c_int),
         ("coarse_steps", ctypes.c_longlong),
+        ("norm_scale", ctypes.c_double),
     ]
 
 
@@ -167,6 +169,8 @@ class Desc:
     Lx: float = 1.0
     vstar: float = 8.0
     steps_override: int = 0
+    nv_y: int = 0                    # 1D3V (separable form) when nv_y, nv_z > 0
+    nv_z: int = 0
 
     def to_c(self):
         keep = [np.ascontiguousarray(self.eps_iface, dtype=np.float64),
@@ -179,7 +183,7 @@ class Desc:
                         int(self.n_slices), int(self.k_max), float(self.tol), float(self.eta0),
                         float(self.delta0), int(self.lift_order), int(self.start_mode),
                         float(self.cfl_theta), int(self.flags), int(self.precision),
-                        int(self.steps_override))
+                        int(self.steps_override), int(self.nv_y), int(self.nv_z))
         return c, keep
 
 

@@ -448,3 +448,32 @@ def test_nonfinite_density_is_reported():
     g.close()
     p.close()
     q.close()
+
+
+def test_1d3v_separable_form_matches_oracle(orc):
+    """1D3V states g(x, vx) M(vy) M(vz) (nv_y = nv_z = 16): the library's
+    fine propagator against the oracle's, with the norm criterion deciding
+    the cell status (the remainder threshold out of reach), so that the 3D
+    norm factor is exercised."""
+    inst = wl.small_hybrid(seed=27, nx=96, nv=32, N=4, T=2e-3)
+    x = wl.cell_centres(96)
+    inst.rho_in = 1.0 + 0.4 * np.cos(2 * np.pi * x) + 0.2 * np.sin(6 * np.pi * x)
+    po0, _, _ = oracle_of(orc, inst)
+    a = orc.lift(po0, inst.eps_iface, inst.rho_in)
+    N1 = orc.diagnostics(po0, inst.eps_iface, inst.eps_cell, inst.rho_in, a)["N"]
+    inst.eta0, inst.delta0 = 1e3, float(np.median(N1)) * 0.25
+    po, ns, _ = orc.setup(inst.nx, inst.nv, inst.eps_iface, inst.rho_in, T=inst.T, N=inst.N,
+                          theta=inst.theta, Lx=inst.Lx, vstar=inst.vstar, eta0=inst.eta0,
+                          delta0=inst.delta0, flags=orc.FIELD | orc.HYBRID, lift_order=inst.lift_order,
+                          start_mode=orc.START_CARRY, nv_y=16, nv_z=16)
+    d = desc_of(inst)
+    d.nv_y = d.nv_z = 16
+    p = sth.Problem(d)
+    assert p.info().norm_scale == pytest.approx(po.norm_scale, rel=1e-14)
+    rg, gg, mg, kg = sth.sth_fine_run(p, inst.rho_in, a, 600)
+    p.close()
+    ro, go, mo, st = orc.fine_propagate(po, inst.eps_iface, inst.eps_cell, inst.rho_in, a, 600)
+    assert np.array_equal(mg, mo) and 0 < mo.sum() < inst.nx
+    assert kg == st["kinetic_iface_steps"]
+    assert rel_err(rg, ro) < RHO64
+    assert rel_err(gg, go) < G64

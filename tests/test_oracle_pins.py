@@ -688,3 +688,56 @@ def test_explicit_and_implicit_coarse_agree_to_first_order(orc):
         pi, _, _ = orc.setup(nx, nv, eps, rho, T=T, N=1, flags=orc.FIELD)
         diffs.append(np.max(np.abs(orc.coarse_step(pe, dtG, rho) - orc.coarse_step(pi, dtG, rho))))
     assert diffs[0] / diffs[1] > 1.9 and diffs[1] / diffs[2] > 1.9
+
+
+# ----------------------------------------------------------------------------- 1D3V
+def _case_1d3v(orc, scale=True, delta0=0.1):
+    nx, nvx, nvy, nvz, vstar = 16, 8, 4, 6, 4.0
+    x = wl.cell_centres(nx)
+    rho = 1.0 + 0.4 * np.cos(2 * np.pi * x) + 0.2 * np.sin(6 * np.pi * x)
+    xi = (np.arange(nx) + 1.0) / nx
+    eps = 1e-3 + 0.5 * (1 + np.tanh((xi - 0.5) / 0.1))
+    epsc = 1e-3 + 0.5 * (1 + np.tanh((x - 0.5) / 0.1))
+    # eta0 out of reach: cells are kinetic through the norm criterion only
+    p, ns, dtG = orc.setup(nx, nvx, eps, rho, T=0.01, N=1, vstar=vstar, eta0=1e3, delta0=delta0,
+                           flags=orc.FIELD | orc.HYBRID, lift_order=1,
+                           nv_y=nvy if scale else 0, nv_z=nvz if scale else 0)
+    a = orc.lift(p, eps, rho)
+    return p, eps, epsc, rho, a, (nvy, nvz, vstar)
+
+
+def test_1d3v_separable_states_reduce_to_1d1v(orc):
+    """The 1D3V scheme on a full 3D velocity grid (brute force, from the
+    paper's 1D3V statement), started from g(x, vx) M(vy) M(vz), stays of that
+    form and equals the 1D1V scheme in vx whose perturbation norms carry the
+    factor sqrt(sum M(vy)^2 dvy sum M(vz)^2 dvz); without that factor the
+    cell status differs (the norm criterion decides here)."""
+    from oracle import oracle3d as o3
+    p, eps, epsc, rho, a, (nvy, nvz, vstar) = _case_1d3v(orc)
+    assert 0.2 < p.norm_scale < 0.3
+    r1, g1, m1, st = orc.fine_propagate(p, eps, epsc, rho, a, 60)
+    r3, g3, m3, k3 = o3.fine_propagate_3d(p, eps, epsc, rho, o3.separable(a, nvy, nvz, vstar), 60, nvy, nvz)
+    assert np.max(np.abs(r3 - r1)) < 1e-13 * np.max(np.abs(r1))
+    assert np.max(np.abs(g3 - o3.separable(g1, nvy, nvz, vstar))) < 1e-12 * np.max(np.abs(g3))
+    assert np.array_equal(m3, m1) and k3 == st["kinetic_iface_steps"]
+    assert 0 < m1.sum() < len(m1)
+    q, *_ = _case_1d3v(orc, scale=False)
+    _, _, m_plain, st_plain = orc.fine_propagate(q, eps, epsc, rho, a, 60)
+    assert not np.array_equal(m_plain, m1)
+    assert st_plain["kinetic_iface_steps"] != st["kinetic_iface_steps"]
+
+
+def test_1d3v_oracle_conserves_mass_and_equilibrium(orc):
+    """Any 3D state (not separable): mass to round-off; the equilibrium
+    (uniform density, no perturbation) stays exactly."""
+    from oracle import oracle3d as o3
+    p, eps, epsc, rho, a, (nvy, nvz, vstar) = _case_1d3v(orc)
+    rng = np.random.default_rng(3)
+    g0 = rng.standard_normal((p.nx, p.nv, nvy, nvz))
+    r, g, m, k = o3.fine_propagate_3d(p, eps, epsc, rho, g0, 40, nvy, nvz)
+    assert abs(r.sum() - rho.sum()) < 1e-13 * rho.sum()
+    assert np.all(np.isfinite(g))
+    flat = np.full(p.nx, 1.0)
+    p.rhobar = 1.0
+    r, g, m, k = o3.fine_propagate_3d(p, eps, epsc, flat, None, 20, nvy, nvz)
+    assert np.array_equal(r, flat) and not np.any(g)

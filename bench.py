@@ -109,6 +109,19 @@ def parse():
     return ap.parse_args()
 
 
+def short_horizon(sth, d, steps):
+    """The description with its horizon cut so that a slice takes about
+    `steps` stable fine steps (warm-ups run the same kernels briefly without
+    forcing an unstable step)."""
+    import copy
+    probe = sth.Problem(d)
+    ns = probe.info().steps_per_slice
+    probe.close()
+    w = copy.copy(d)
+    w.T = d.T * min(1.0, steps / ns)
+    return w
+
+
 def cpu_baseline(inst, target_s):
     """The CPU oracle (plain FP64 C, OpenMP over slices as in the paper's
     implementation) on a bounded sample of the same work: the first slices of
@@ -178,7 +191,7 @@ def run_batch(args, torch, sth, wl):
               f"{tune_info['changed']} changed, speedup {tune_info['class_speedup_geomean']:.3f} geomean",
               file=sys.stderr, flush=True)
     if args.warmup > 0:  # every kernel class once, short slices
-        ws = [sth.Problem(desc(i, prec, steps_override=20)) for i in insts]
+        ws = [sth.Problem(short_horizon(sth, desc(i, prec), 20)) for i in insts]
         for w in ws:
             sth.sth_coarse_sweep(w, stream)
         sth.sth_fine_sweep_batched(ws, stream)
@@ -293,7 +306,7 @@ def run_serve(args, torch, sth, wl):
     # warmup: every kernel class once
     warm = [serving.Request(r, desc(i, sth.FP32_BULK), 0.0, 1) for r, i in enumerate(insts[:48])]
     for w in warm:
-        w.desc.steps_override = 20
+        w.desc = short_horizon(sth, w.desc, 20)
     srv.run(warm)
     torch.cuda.synchronize()
 
@@ -488,7 +501,7 @@ def main():
     stream = torch.cuda.Stream()
     # warmup: same kernels on a separate problem with short slices
     if args.warmup > 0:
-        w = sth.Problem(desc(steps_override=2000))
+        w = sth.Problem(short_horizon(sth, desc(), 2000))
         sth.sth_coarse_sweep(w, stream)
         for _ in range(min(args.warmup, inst.N)):
             sth.sth_fine_sweep_batched([w], stream)

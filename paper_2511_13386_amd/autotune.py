@@ -46,14 +46,18 @@ class ClassResult:
 
 def _probe_desc(key: ClassKey, units: int, steps: int) -> sth.Desc:
     """A hybrid problem of the class (the tanh eps profile of the hybrid
-    workload) with `units` slices of `steps` steps each."""
+    workload) with `units` slices of about `steps` stable steps each."""
     prec, nx, nv = key
     inst = wl.config2(seed=0, nx=nx, nv=nv, N=int(units), T=1e-3, K=1)
-    return sth.Desc(nx=nx, nv=nv, eps_iface=inst.eps_iface, eps_cell=inst.eps_cell,
-                    rho0=inst.rho_in, T=inst.T, n_slices=int(units), k_max=1,
-                    eta0=inst.eta0, delta0=inst.delta0, flags=sth.FIELD | sth.HYBRID,
-                    precision=prec, start_mode=sth.START_CARRY, cfl_theta=inst.theta,
-                    steps_override=int(steps))
+    d = sth.Desc(nx=nx, nv=nv, eps_iface=inst.eps_iface, eps_cell=inst.eps_cell,
+                 rho0=inst.rho_in, T=inst.T, n_slices=int(units), k_max=1,
+                 eta0=inst.eta0, delta0=inst.delta0, flags=sth.FIELD | sth.HYBRID,
+                 precision=prec, start_mode=sth.START_CARRY, cfl_theta=inst.theta)
+    probe = sth.Problem(d)
+    ns = probe.info().steps_per_slice
+    probe.close()
+    d.T = d.T * steps / ns
+    return d
 
 
 def tune_class(key: ClassKey, units: int, steps: int = 200, repeats: int = 3,

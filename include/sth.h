@@ -7,6 +7,18 @@
  * Model (1D1V): eps(x) d_t f + v d_x f + E d_v f = (rho M - f)/eps on the torus
  * [0, Lx) x [-vstar, vstar], with f = rho M + eps g (g is the scaled
  * perturbation), Gauss law E_{i+1/2} - E_{i-1/2} = (rho_i - rhobar) dx.
+ * The 1D3V problem of the paper (velocity in [-vstar, vstar]^3, field along
+ * x) is available for states g(x, vx) M(vy) M(vz) (sth_problem_desc.nv_y,
+ * nv_z).
+ *
+ * Entry points: problem set-up (sth_footprint_bytes, sth_create,
+ * sth_destroy), the coarse guess (sth_coarse_sweep[_batched]), the fine
+ * propagator over all unconverged slices of a batch (sth_fine_sweep_batched,
+ * or in chunks of steps: sth_fine_sweep_chunk), the parareal correction
+ * (sth_parareal_correct[_batched]), whole solves recorded as HIP graphs
+ * (sth_graph_*), per-class launch configuration (sth_*_fine_config*),
+ * diagnostics and results (sth_moments_criteria, sth_get_rho, sth_get_g,
+ * sth_get_errors, sth_get_info, sth_fine_run).
  * rho lives at cell centres x_i = (i+1/2) dx, g at interfaces x_p = (p+1) dx
  * (interface p separates cells p and p+1; it is "i+1/2" for i = p).
  *

@@ -83,10 +83,13 @@ def parse():
     ap.add_argument("--T", type=float, default=1.0)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--unit-steps", type=int, default=2000, help="unit: fine steps of the one slice")
+    ap.add_argument("--unit-hybrid", action="store_true", help="unit: domain adaptation on")
     ap.add_argument("--no-other-precision", action="store_true",
                     help="config2: skip the same solve in the other precision")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--workload", choices=["config2", "batch", "serve", "convergence", "1d3v"], default="config2",
+    ap.add_argument("--workload", choices=["config2", "batch", "serve", "convergence", "1d3v", "unit"],
+                    default="config2",
                     help="config2: the hybrid parareal problem the metric is quoted on; "
                          "batch: many independent instances in one batched sweep per iteration")
     ap.add_argument("--batch-count", type=int, default=256)
@@ -460,6 +463,35 @@ def run_1d3v(args, torch, sth, wl):
     print(json.dumps(out), flush=True)
 
 
+def run_unit(args, torch, sth, wl):
+    """Step latency of one slice (one workgroup) of --nx x --nv in the chosen
+    precision, all kinetic unless --unit-hybrid: the per-step cost that
+    bounds a long slice, and a single fine-kernel launch for counters."""
+    prec = sth.FP64 if args.precision == "fp64" else sth.FP32_BULK
+    inst = wl.config2(seed=args.seed, nx=args.nx, nv=args.nv, N=4, T=1e-3)
+    d = sth.Desc(nx=inst.nx, nv=inst.nv, eps_iface=inst.eps_iface, eps_cell=inst.eps_cell, rho0=inst.rho_in,
+                 T=inst.T, n_slices=4, flags=sth.FIELD | (sth.HYBRID if args.unit_hybrid else 0),
+                 precision=prec, cfl_theta=inst.theta)
+    p = sth.Problem(d)
+    info = p.info()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, _, kin = sth.sth_fine_run(p, inst.rho_in, None, args.unit_steps)
+    el = time.perf_counter() - t0
+    p.close()
+    us = el * 1e6 / args.unit_steps
+    realsz = 8 if prec == sth.FP64 else 4
+    out = {"metric": "fine step latency of one slice", "value": us, "unit": "us/step", "n_gpus": 1,
+           "steps": args.unit_steps, "warmup": 0, "higher_is_better": False, "data": "synthetic",
+           "dtype": "f64" if prec == sth.FP64 else "f32-bulk/f64-macro",
+           "config": {"workload": f"one slice {inst.nx}x{inst.nv}, {'hybrid' if args.unit_hybrid else 'all kinetic'}",
+                      "fine_block": info.fine_block, "fine_form": "resident rows" if info.fine_resident
+                      else "streamed rows"},
+           "kinetic_cell_updates_per_s": kin * inst.nv / el,
+           "slot_gb_per_s": kin * inst.nv * 2 * realsz / el / 1e9}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -485,6 +517,9 @@ def main():
         return
     if args.workload == "1d3v":
         run_1d3v(args, torch, sth, wl)
+        return
+    if args.workload == "unit":
+        run_unit(args, torch, sth, wl)
         return
     prec = sth.FP64 if args.precision == "fp64" else sth.FP32_BULK
     inst = wl.config2(seed=args.seed, nx=args.nx, nv=args.nv, N=args.slices, T=args.T,

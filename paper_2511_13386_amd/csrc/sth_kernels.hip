@@ -518,9 +518,10 @@ __device__ __forceinline__ RowOut<Real> row_pass_res(Real (&Wr)[NV], const RowCo
 //       turning fluid drop their perturbation), density update with the
 //       fluxes of step n-1, wave prefix sums of (rho - rhobar) dx     | B1
 //   P2  field E (Gauss law, zero-mean gauge), cell-centred flux J      | B2
-//   P3  remainder criterion of every cell; phase-space pass of every
-//       segment with a kinetic interface: transport, projection,
-//       relaxation, flux Phi and the norm of g                         | B3
+//   P3  phase-space pass of every segment with a kinetic interface:
+//       transport, projection, relaxation, flux Phi and the norm of g;
+//       remainder criterion of every cell (after the pass, by the first
+//       half of the wavefronts, which the SIMDs serve first)            | B3
 // RES: resident form (rows in registers, halos and c1 in LDS), for units
 // whose rows fit in the registers of their lanes; otherwise the rows stream
 // from the unit slot every step.
@@ -806,32 +807,47 @@ __global__ void __launch_bounds__(BLK) k_fine(const FineUnit *__restrict__ units
     };
     // Remainder R_i (eq. RemainderBis, Table 1 stencils) of the current
     // density and its criterion bit.
-    auto macro_crit = [&]() {
+    auto crit_cell = [&](int i, double mJ) {
         const double inv_dx2 = inv_dx * inv_dx, inv_dx3 = inv_dx2 * inv_dx;
-        const double eta0 = C->eta0;
+        const double r = s_rho[i];
+        const double jc = s_jc[i];
+        const double d1J = fd1g(s_jc + i) * inv_dx;
+        const double d3J = fd3g(s_jc + i) * inv_dx3;
+        double R;
+        if (field) {
+            const double Ec = s_E[i] - 0.5 * (r - rhobar) * dx;
+            const double d1r = fd1g(s_rho + i) * inv_dx;
+            const double d2J = fd2g(s_jc + i) * inv_dx2;
+            R = -d3J + Ec * d2J + (2.0 * r - 3.0 * rhobar) * d1J + 2.0 * jc * d1r - d1r * (jc - mJ);
+        } else {
+            R = -d3J;
+        }
+        const double ec = g_epsc[i];
+        const double crit = literal ? fabs(R) : ec * ec * fabs(R);
+        s_crit[i] = (unsigned char)(crit > C->eta0);
+        *(i == 0 ? s_crit + nx : s_sink8 + lane) = (unsigned char)(crit > C->eta0);
+    };
+    auto macro_crit = [&]() {
         const double mJ = wave_total_f64(lane < nslot ? s_jtot[lane] : 0.0) * inv_nx;
 #pragma unroll
         for (int k = 0; k < IPTM; ++k) {
             const int i = k * BS + tid;
-            if (k < ipt && i < nx) {
-                const double r = s_rho[i];
-                const double jc = s_jc[i];
-                const double d1J = fd1g(s_jc + i) * inv_dx;
-                const double d3J = fd3g(s_jc + i) * inv_dx3;
-                double R;
-                if (field) {
-                    const double Ec = s_E[i] - 0.5 * (r - rhobar) * dx;
-                    const double d1r = fd1g(s_rho + i) * inv_dx;
-                    const double d2J = fd2g(s_jc + i) * inv_dx2;
-                    R = -d3J + Ec * d2J + (2.0 * r - 3.0 * rhobar) * d1J + 2.0 * jc * d1r
-                        - d1r * (jc - mJ);
-                } else {
-                    R = -d3J;
-                }
-                const double ec = g_epsc[i];
-                const double crit = literal ? fabs(R) : ec * ec * fabs(R);
-                s_crit[i] = (unsigned char)(crit > eta0);
-                *(i == 0 ? s_crit + nx : s_sink8 + lane) = (unsigned char)(crit > eta0);
+            if (k < ipt && i < nx) crit_cell(i, mJ);
+        }
+    };
+    // The same for every cell, by the first half of the wavefronts (each
+    // lane takes its own cells and those of the lane BS/2 further): called
+    // after the row pass, where the SIMDs' first wavefronts would otherwise
+    // wait at the barrier for the second ones, which the scheduler serves
+    // later.
+    auto macro_crit_half = [&]() {
+        const double mJ = wave_total_f64(lane < nslot ? s_jtot[lane] : 0.0) * inv_nx;
+#pragma unroll
+        for (int k = 0; k < IPTM; ++k) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int i = k * BS + tid + h * (BS / 2);
+                if (k < ipt && i < nx) crit_cell(i, mJ);
             }
         }
     };
@@ -945,8 +961,10 @@ __global__ void __launch_bounds__(BLK) k_fine(const FineUnit *__restrict__ units
         // P2: field and cell-centred flux.
         macro_field();
         __syncthreads();  // B2
-        // P3: criterion bits, then the phase-space pass.
-        if (hybrid) macro_crit();
+        // P3: the phase-space pass and the criterion bits (before the pass
+        // when the workgroup has one wavefront or an odd count).
+        const bool crit_after = NW >= 2 && (NW & 1) == 0;
+        if (hybrid && !crit_after) macro_crit();
         // one slab k: coefficients, row pass of a segment with a kinetic
         // interface, flux and norm
         auto slab = [&](int k, auto &&pass) {
@@ -1042,6 +1060,7 @@ __global__ void __launch_bounds__(BLK) k_fine(const FineUnit *__restrict__ units
                 });
             }
         }
+        if (hybrid && crit_after && wid < NW / 2) macro_crit_half();
         __syncthreads();  // B3
     }
 

@@ -18,7 +18,7 @@
  * (sth_parareal_correct[_batched]), whole solves recorded as HIP graphs
  * (sth_graph_*), per-class launch configuration (sth_*_fine_config*),
  * diagnostics and results (sth_moments_criteria, sth_get_rho, sth_get_g,
- * sth_get_errors, sth_get_info, sth_fine_run).
+ * sth_get_errors, sth_get_info, sth_fine_run[_masks]).
  * rho lives at cell centres x_i = (i+1/2) dx, g at interfaces x_p = (p+1) dx
  * (interface p separates cells p and p+1; it is "i+1/2" for i = p).
  *
@@ -39,6 +39,7 @@
 #define STH_H
 
 #include <stddef.h>
+#include <stdint.h>
 
 #ifdef __cplusplus
 extern "C" {
@@ -286,6 +287,22 @@ int  sth_get_info(const sth_problem *p, sth_info *out);
 int  sth_fine_run(sth_problem *p, const double *rho_in, const double *g_in, long long nsteps,
                   double *rho_out, double *g_out, int *cell_mask_out, double *kin_out,
                   void *stream);
+
+/* sth_fine_run with the cell status of every step exposed (the kinetic
+ * region of Section 2.2, decided by the rule of that section on the data of
+ * step n - 1 and applied at step n).  Row n (n = 0..nsteps) is the status
+ * applied at step n, row nsteps the status after the last step; a row is
+ * (nx + 63) / 64 words, bit (i mod 64) of word i / 64 set for a kinetic cell
+ * i.  mask_hist (device memory, or NULL) receives the rows; mask_replay
+ * (device memory, or NULL) imposes them instead of the rule, so that runs
+ * in two precisions can share one sequence of kinetic regions and their
+ * difference is then precision alone.  Both need STH_HYBRID (else
+ * STH_EINVAL); host pointers there are STH_EINVAL.  Both arrays hold
+ * (nsteps + 1) rows; the caller owns them.  Synchronises. */
+int  sth_fine_run_masks(sth_problem *p, const double *rho_in, const double *g_in, long long nsteps,
+                        const uint64_t *mask_replay, uint64_t *mask_hist,
+                        double *rho_out, double *g_out, int *cell_mask_out, double *kin_out,
+                        void *stream);
 
 /* Release the problem (and its device memory if the library allocated it). */
 void sth_destroy(sth_problem *p);

@@ -87,6 +87,9 @@ def lib():
         L.orc_diagnostics.argtypes = [_P, _D, _D, _D, _D, _D, _D, _D, _D, _D, _I]
         L.orc_fine_propagate.argtypes = [_P, _D, _D, _D, _D, ctypes.c_long, _D, _D, _I,
                                          ctypes.POINTER(Stats)]
+        _U8 = ctypes.POINTER(ctypes.c_uint8)
+        L.orc_fine_propagate_masks.argtypes = [_P, _D, _D, _D, _D, ctypes.c_long, _U8, _U8, _D, _D, _I,
+                                               ctypes.POINTER(Stats)]
         L.orc_coarse_step.argtypes = [_P, ctypes.c_double, _D, _D]
         L.orc_cyclic_tridiag.argtypes = [ctypes.c_int, _D, _D, _D, _D, _D]
         L.orc_cyclic_tridiag.restype = ctypes.c_int
@@ -206,6 +209,37 @@ def fine_propagate(p: Params, eps_iface, eps_cell, rho_in, g_in, nsteps):
                              ctypes.byref(st))
     return rho, g, mask, {"kinetic_iface_steps": st.kinetic_iface_steps,
                           "mask_flips": st.mask_flips, "final_kinetic": st.final_kinetic}
+
+
+def fine_propagate_masks(p: Params, eps_iface, eps_cell, rho_in, g_in, nsteps, replay=None):
+    """fine_propagate with the cell status of every step: returns (rho, g,
+    cell_mask, stats, hist) with hist[n, i] = 1 if cell i is kinetic at step n
+    (n = 0..nsteps).  replay ([nsteps+1, nx], nonzero = kinetic) imposes the
+    statuses instead of the rule.  Hybrid runs only."""
+    if not p.flags & HYBRID:
+        raise ValueError("cell status history needs the hybrid flag")
+    eps_iface, eps_cell, rho_in = map(_f64, (eps_iface, eps_cell, rho_in))
+    g_ptr = None
+    if g_in is not None:
+        g_in = _f64(g_in)
+        g_ptr = _d(g_in)
+    u8 = ctypes.POINTER(ctypes.c_uint8)
+    rp = None
+    if replay is not None:
+        replay = np.ascontiguousarray(np.asarray(replay) != 0, dtype=np.uint8)
+        if replay.shape != (int(nsteps) + 1, p.nx):
+            raise ValueError("replay must have shape (nsteps + 1, nx)")
+        rp = replay.ctypes.data_as(u8)
+    hist = np.zeros((int(nsteps) + 1, p.nx), dtype=np.uint8)
+    rho = np.zeros(p.nx)
+    g = np.zeros((p.nx, p.nv))
+    mask = np.zeros(p.nx, dtype=np.int32)
+    st = Stats()
+    lib().orc_fine_propagate_masks(ctypes.byref(p), _d(eps_iface), _d(eps_cell), _d(rho_in), g_ptr,
+                                   int(nsteps), rp, hist.ctypes.data_as(u8), _d(rho), _d(g),
+                                   mask.ctypes.data_as(_I), ctypes.byref(st))
+    return rho, g, mask, {"kinetic_iface_steps": st.kinetic_iface_steps,
+                          "mask_flips": st.mask_flips, "final_kinetic": st.final_kinetic}, hist
 
 
 def coarse_step(p: Params, dtG, rho_in):

@@ -363,6 +363,21 @@ void orc_fine_propagate(const orc_params *p, const double *eps_iface, const doub
                         const double *rho_in, const double *g_in, long nsteps,
                         double *rho_out, double *g_out, int *cell_mask_out, orc_stats *st)
 {
+    orc_fine_propagate_masks(p, eps_iface, eps_cell, rho_in, g_in, nsteps, NULL, NULL,
+                             rho_out, g_out, cell_mask_out, st);
+}
+
+/* The same propagator with the cell status of every step exposed: hist
+ * (if not NULL) receives the status applied at step n in row n, n = 0..nsteps
+ * (row nsteps: the status after the last step); replay (if not NULL) supplies
+ * those rows instead of the rule of Section 2.2, so that two runs can share
+ * one sequence of kinetic regions.  Rows are nx bytes (1 = kinetic cell);
+ * both need the hybrid flag. */
+void orc_fine_propagate_masks(const orc_params *p, const double *eps_iface, const double *eps_cell,
+                              const double *rho_in, const double *g_in, long nsteps,
+                              const unsigned char *replay, unsigned char *hist,
+                              double *rho_out, double *g_out, int *cell_mask_out, orc_stats *st)
+{
     int nx = p->nx, nv = p->nv;
     int hybrid = (p->flags & ORC_HYBRID) != 0, field = (p->flags & ORC_FIELD) != 0;
     double dx = p->Lx / nx, dv = 2.0 * p->vstar / nv, dt = p->dt;
@@ -397,6 +412,8 @@ void orc_fine_propagate(const orc_params *p, const double *eps_iface, const doub
             double nl = N[wrap(i - 1, nx)], nr = N[i];
             double nmax = nl > nr ? nl : nr;
             cell[i] = (nmax > p->delta0) || (crit_R(p, eps_cell[i], R[i]) > p->eta0);
+            if (replay) cell[i] = replay[i] != 0;
+            if (hist) hist[i] = (unsigned char)cell[i];
         }
         for (int q = 0; q < nx; ++q) {
             ifc[q] = cell[q] || cell[wrap(q + 1, nx)];
@@ -425,6 +442,8 @@ void orc_fine_propagate(const orc_params *p, const double *eps_iface, const doub
                 } else {
                     ncell[i] = c > p->eta0;
                 }
+                if (replay) ncell[i] = replay[(size_t)(n + 1) * nx + i] != 0;
+                if (hist) hist[(size_t)(n + 1) * nx + i] = (unsigned char)ncell[i];
             }
             for (int q = 0; q < nx; ++q) nifc[q] = ncell[q] || ncell[wrap(q + 1, nx)];
         }

@@ -106,6 +106,13 @@ void   orc_fine_propagate(const orc_params *p, const double *eps_iface, const do
                           const double *rho_in, const double *g_in, long nsteps,
                           double *rho_out, double *g_out, int *cell_mask_out, orc_stats *st);
 
+/* the same with the per-step cell status recorded (hist) or imposed
+ * (replay), each [(nsteps+1)][nx] bytes or NULL; hybrid runs only */
+void   orc_fine_propagate_masks(const orc_params *p, const double *eps_iface, const double *eps_cell,
+                                const double *rho_in, const double *g_in, long nsteps,
+                                const unsigned char *replay, unsigned char *hist,
+                                double *rho_out, double *g_out, int *cell_mask_out, orc_stats *st);
+
 /* coarse G over one interval dtG: one backward-Euler drift-diffusion step
  * with frozen field, or (ORC_COARSE_EXPLICIT) coarse_steps steps of the
  * explicit limit scheme S^0 */

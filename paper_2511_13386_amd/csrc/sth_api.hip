@@ -28,6 +28,18 @@ int fail(int code, const std::string &msg)
     return code;
 }
 
+// Device (or managed) memory, as a kernel argument must be; a host pointer
+// makes the query fail, and its error is cleared here.
+bool is_device_ptr(const void *ptr)
+{
+    hipPointerAttribute_t a{};
+    if (hipPointerGetAttributes(&a, ptr) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
 int hip_fail(hipError_t e, const char *where)
 {
     return fail(STH_EHIP, std::string(where) + ": " + hipGetErrorString(e));
@@ -1354,8 +1366,20 @@ int sth_get_info(const sth_problem *p, sth_info *out)
 int sth_fine_run(sth_problem *p, const double *rho_in, const double *g_in, long long nsteps,
                  double *rho_out, double *g_out, int *cell_mask_out, double *kin_out, void *stream)
 {
+    return sth_fine_run_masks(p, rho_in, g_in, nsteps, nullptr, nullptr, rho_out, g_out, cell_mask_out,
+                              kin_out, stream);
+}
+
+int sth_fine_run_masks(sth_problem *p, const double *rho_in, const double *g_in, long long nsteps,
+                       const uint64_t *mask_replay, uint64_t *mask_hist, double *rho_out, double *g_out,
+                       int *cell_mask_out, double *kin_out, void *stream)
+{
     if (!p || !rho_in) return fail(STH_EINVAL, "null argument");
     if (nsteps < 0) return fail(STH_EINVAL, "nsteps must be >= 0");
+    if ((mask_replay || mask_hist) && !(p->flags & STH_HYBRID))
+        return fail(STH_EINVAL, "a cell status history needs STH_HYBRID");
+    if (mask_replay && !is_device_ptr(mask_replay)) return fail(STH_EINVAL, "mask_replay must be device memory");
+    if (mask_hist && !is_device_ptr(mask_hist)) return fail(STH_EINVAL, "mask_hist must be device memory");
     hipStream_t st = (hipStream_t)stream;
     const int nx = p->nx;
     HIPCHK(hipDeviceSynchronize());
@@ -1379,6 +1403,8 @@ int sth_fine_run(sth_problem *p, const double *rho_in, const double *g_in, long 
     u.kin = d_kin;
     u.mask_out = p->at<int>(p->L.mask);
     u.nsteps = nsteps;
+    u.mask_replay = (const unsigned long long *)mask_replay;
+    u.mask_hist = (unsigned long long *)mask_hist;
     if (nsteps == 0) {
         // a zero-step run returns the initial state after the status rule
         u.nsteps = 0;

@@ -67,6 +67,12 @@ struct FineUnit {
     // instead of the outputs.
     long long step0, step1;
     double *ckpt;             // [kCkptArrays][nx] when the slice is chunked
+    // Cell status of every step n = 0..nsteps (row n: the status applied at
+    // step n, row nsteps: after the last), one bit per cell, rows of
+    // (nx + 63) / 64 words: recorded into mask_hist and/or imposed from
+    // mask_replay instead of the rule (hybrid runs; NULL in the sweeps).
+    const unsigned long long *mask_replay;
+    unsigned long long *mask_hist;
 };
 // Checkpoint of a suspended unit: rho, its compensation, Phi, m2 J, the
 // norms, the cell status of the last step and the criterion bits, each nx

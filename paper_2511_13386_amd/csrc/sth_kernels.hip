@@ -857,9 +857,10 @@ __global__ void __launch_bounds__(BLK) k_fine(const FineUnit *__restrict__ units
     // turns kinetic on the criterion.  Each thread evaluates its cell i and
     // cell i+1, which fixes the status of interface i; interfaces turning
     // fluid get g' = 0 (row, lazy projection, halos of both parities).
-    auto status = [&](int par) {
+    auto status = [&](int par, long long n) {
         const double delta0 = C->delta0;
         const unsigned char *cm_old = s_cm + (par ^ 1) * ncm;
+        const int mw = (nx + kWave - 1) / kWave;
 #pragma unroll
         for (int k = 0; k < IPTM; ++k) {
             const int i = k * BS + tid;
@@ -868,8 +869,20 @@ __global__ void __launch_bounds__(BLK) k_fine(const FineUnit *__restrict__ units
                 const double Nm = (double)s_nrm[i - 1], N0 = (double)s_nrm[i], Np = (double)s_nrm[i + 1];
                 const unsigned cr0 = s_crit[i], cr1 = s_crit[i + 1], co0 = cm_old[i], co1 = cm_old[i + 1];
                 const double n0 = Nm > N0 ? Nm : N0, n1 = N0 > Np ? N0 : Np;
-                const int ci = (int)(cr0 | (co0 & (n0 > delta0 ? 1u : 0u)));
-                const int cn = (int)(cr1 | (co1 & (n1 > delta0 ? 1u : 0u)));
+                int ci = (int)(cr0 | (co0 & (n0 > delta0 ? 1u : 0u)));
+                int cn = (int)(cr1 | (co1 & (n1 > delta0 ? 1u : 0u)));
+                if (U.mask_replay || U.mask_hist) {
+                    const size_t row = (size_t)n * mw;
+                    if (U.mask_replay) {
+                        const int i1 = i + 1 == nx ? 0 : i + 1;
+                        ci = (int)((U.mask_replay[row + (i >> 6)] >> (i & 63)) & 1ull);
+                        cn = (int)((U.mask_replay[row + (i1 >> 6)] >> (i1 & 63)) & 1ull);
+                    }
+                    // the cells of a wavefront are 64 consecutive ones from a
+                    // multiple of 64: one word per wavefront
+                    const unsigned long long b = __ballot(ci != 0);
+                    if (U.mask_hist && lane == 0) U.mask_hist[row + (i >> 6)] = b;
+                }
                 s_cm[par * ncm + i] = (unsigned char)ci;
                 *(i == 0 ? s_cm + par * ncm + nx : s_sink8 + lane) = (unsigned char)ci;
                 cmbits = (cmbits & ~(1u << k)) | ((unsigned)ci << k);
@@ -954,7 +967,7 @@ __global__ void __launch_bounds__(BLK) k_fine(const FineUnit *__restrict__ units
         lane = tid & (kWave - 1);
         // P1: status of step n, density at step n, prefix sums.
         const unsigned cm_prev = cmbits;
-        if (hybrid) status(par);
+        if (hybrid) status(par, n);
         if (n > 0) density_update(cm_prev);
         macro_scan();
         __syncthreads();  // B1
@@ -1075,7 +1088,7 @@ __global__ void __launch_bounds__(BLK) k_fine(const FineUnit *__restrict__ units
     const int fpar = (int)(step1 & 1);
     const unsigned cm_last = cmbits;
     if (!suspend) {
-        if (hybrid) status(fpar);
+        if (hybrid) status(fpar, step1);
         if (nsteps > 0) density_update(cm_last);
     }
     double *ck = U.ckpt;

@@ -31,7 +31,7 @@ EXPORTS = (
     "sth_fine_run", "sth_destroy", "sth_last_error", "sth_parareal_correct_batched", "sth_get_errors",
     "sth_graph_create", "sth_graph_launch", "sth_graph_wait", "sth_graph_destroy",
     "sth_fine_config_candidates", "sth_set_fine_config", "sth_get_fine_config",
-    "sth_coarse_sweep_batched", "sth_fine_sweep_chunk",
+    "sth_coarse_sweep_batched", "sth_fine_sweep_chunk", "sth_fine_run_masks",
 )
 
 
@@ -110,6 +110,8 @@ def lib() -> ctypes.CDLL:
         L.sth_get_info.argtypes = [_VP, ctypes.POINTER(Info)]
         L.sth_fine_run.argtypes = [_VP, _D, _D, ctypes.c_longlong, _D, _D,
                                    ctypes.POINTER(ctypes.c_int), _D, _VP]
+        L.sth_fine_run_masks.argtypes = [_VP, _D, _D, ctypes.c_longlong, _VP, _VP, _D, _D,
+                                         ctypes.POINTER(ctypes.c_int), _D, _VP]
         L.sth_parareal_correct_batched.argtypes = [ctypes.POINTER(_VP), ctypes.c_int, _D, _VP]
         L.sth_get_errors.argtypes = [_VP, _D]
         L.sth_graph_create.argtypes = [ctypes.POINTER(_VP), ctypes.c_int, ctypes.POINTER(_VP)]
@@ -379,6 +381,48 @@ def sth_fine_run(p: Problem, rho_in, g_in, nsteps: int, stream=None):
                               mask.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), ctypes.byref(kin),
                               _stream(stream)))
     return rho, g, mask, kin.value
+
+
+def sth_fine_run_masks(p: Problem, rho_in, g_in, nsteps: int, replay=None, stream=None):
+    """sth_fine_run with the cell status of every step: returns (rho, g,
+    cell_mask, kin, hist), hist[n, i] = 1 if cell i is kinetic at step n
+    (n = 0..nsteps).  replay ([nsteps + 1, nx], nonzero = kinetic) imposes
+    those statuses instead of the rule.  The bit rows live in torch device
+    tensors for the call."""
+    import torch
+    nsteps = int(nsteps)
+    rho_in = np.ascontiguousarray(rho_in, dtype=np.float64)
+    g_arr = None if g_in is None else np.ascontiguousarray(g_in, dtype=np.float64)
+    mw = (p.nx + 63) // 64
+    rows = nsteps + 1
+
+    def pack(m):
+        m = np.asarray(m) != 0
+        if m.shape != (rows, p.nx):
+            raise ValueError("replay must have shape (nsteps + 1, nx)")
+        bits = np.zeros((rows, mw * 64), dtype=np.uint8)
+        bits[:, :p.nx] = m
+        # little-endian words: bit i of a row is bit (i mod 64) of word i / 64
+        return np.packbits(bits, axis=-1, bitorder="little").view("<u8")
+
+    dev = torch.device("cuda", torch.cuda.current_device())
+    d_rep = None
+    if replay is not None:
+        d_rep = torch.from_numpy(pack(replay).view(np.int64)).to(dev)
+    d_hist = torch.zeros((rows, mw), dtype=torch.int64, device=dev)
+    rho = np.zeros(p.nx)
+    g = np.zeros((p.nx, p.nv))
+    mask = np.zeros(p.nx, dtype=np.int32)
+    kin = ctypes.c_double()
+    torch.cuda.synchronize(dev)
+    _check(lib().sth_fine_run_masks(p.h, _d(rho_in), _d(g_arr), nsteps,
+                                    None if d_rep is None else d_rep.data_ptr(), d_hist.data_ptr(),
+                                    _d(rho), _d(g), mask.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                    ctypes.byref(kin), _stream(stream)))
+    words = np.ascontiguousarray(d_hist.cpu().numpy()).view("<u8")
+    bits = np.unpackbits(words.view(np.uint8), axis=-1, bitorder="little")
+    hist = bits[:, :p.nx].astype(np.uint8)
+    return rho, g, mask, kin.value, hist
 
 
 def sth_destroy(p: Problem) -> None:

@@ -1,0 +1,135 @@
+"""Cell status history and replay through the C-ABI (sth_fine_run_masks).
+
+The kinetic region of every step (Section 2.2's rule on the data of step
+n - 1, applied at step n) is recorded one bit per cell.  In FP64 the GPU's
+history equals the oracle's step for step.  In FP32 bulk, rounding can move
+a criterion across its threshold; the number of (step, cell) disagreements
+with the FP64 oracle is reported, and the FP32 run is repeated with the
+oracle's history imposed, so that what is left is the precision error
+alone, held to the FP32-bulk tolerances (density 2e-6, perturbation 2e-4
+relative)."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_2511_13386_amd import sth
+from paper_2511_13386_amd import workloads as wl
+
+from helpers import desc_of, oracle_of, rel_err
+
+pytestmark = pytest.mark.gpu
+
+RHO64, G64 = 1e-12, 1e-10
+RHO32, G32 = 2e-6, 2e-4
+
+
+@pytest.fixture
+def clean_table():
+    touched = []
+    yield touched
+    for prec, nx, nv in touched:
+        sth.sth_set_fine_config(prec, nx, nv, None)
+
+
+def _oracle_hist(orc, inst, steps, replay=None):
+    po, _, _ = oracle_of(orc, inst)
+    return orc.fine_propagate_masks(po, inst.eps_iface, inst.eps_cell, inst.rho_in, None, steps,
+                                    replay=replay)
+
+
+@pytest.mark.parametrize("nx,nv,steps,cfg", [
+    (96, 32, 3000, None),          # resident, ragged segment
+    (200, 16, 1500, (128, 0)),     # streamed, two interfaces per thread
+    (200, 16, 1500, (64, 1)),      # resident, four interfaces per thread
+    (1100, 32, 300, (1024, 0)),    # wide streamed workgroups
+])
+def test_fp64_history_is_the_oracles(orc, clean_table, nx, nv, steps, cfg):
+    inst = wl.small_hybrid(nx=nx, nv=nv)
+    if cfg is not None:
+        sth.sth_set_fine_config(sth.FP64, nx, nv, cfg)
+        clean_table.append((sth.FP64, nx, nv))
+    ro, go, mo, st, ho = _oracle_hist(orc, inst, steps)
+    if nx <= 200:   # long enough for the rule to switch cells (the wide case stays kinetic)
+        assert 0 < ho.sum() < ho.size and np.any(ho[1:] != ho[:-1])
+    p = sth.Problem(desc_of(inst))
+    rg, gg, mg, kg, hg = sth.sth_fine_run_masks(p, inst.rho_in, None, steps)
+    assert np.array_equal(hg, ho)
+    assert np.array_equal(mg, mo) and kg == st["kinetic_iface_steps"]
+    assert rel_err(rg, ro) < RHO64 and rel_err(gg, go) < G64
+    # the plain run takes the same decisions, and imposing them changes nothing
+    r0, g0, m0, k0 = sth.sth_fine_run(p, inst.rho_in, None, steps)
+    r1, g1, m1, k1, h1 = sth.sth_fine_run_masks(p, inst.rho_in, None, steps, replay=ho)
+    p.close()
+    for a, b in ((r0, rg), (g0, gg), (r1, rg), (g1, gg), (h1, ho)):
+        assert np.array_equal(a, b)
+    assert k0 == k1 == kg
+
+
+def test_imposed_history_decides(orc):
+    """A history that differs from the rule's is followed: the GPU and the
+    oracle, both replaying it, agree, and differ from the plain run."""
+    inst = wl.small_hybrid(nx=96, nv=32)
+    steps = 600
+    _, _, _, _, ho = _oracle_hist(orc, inst, steps)
+    hf = ho.copy()
+    hf[steps // 2:, 40:43] = 0
+    hf[steps // 3, 70:80] = 1
+    ro, go, _, st, ho2 = _oracle_hist(orc, inst, steps, replay=hf)
+    assert np.array_equal(ho2, hf)
+    p = sth.Problem(desc_of(inst))
+    rg, gg, mg, kg, hg = sth.sth_fine_run_masks(p, inst.rho_in, None, steps, replay=hf)
+    r0, _, _, _ = sth.sth_fine_run(p, inst.rho_in, None, steps)
+    p.close()
+    assert np.array_equal(hg, hf) and np.array_equal(mg, hf[-1])
+    assert kg == st["kinetic_iface_steps"]
+    assert rel_err(rg, ro) < RHO64 and rel_err(gg, go) < G64
+    assert rel_err(r0, rg) > 1e-9
+    # the same imposed history in FP32 bulk
+    p = sth.Problem(desc_of(inst, precision=sth.FP32_BULK))
+    r32, g32, m32, k32, h32 = sth.sth_fine_run_masks(p, inst.rho_in, None, steps, replay=hf)
+    p.close()
+    assert np.array_equal(h32, hf) and k32 == st["kinetic_iface_steps"]
+    assert rel_err(r32, ro) < RHO32 and rel_err(g32, go) < G32
+
+
+@pytest.mark.parametrize("nx,nv,steps,cfg", [
+    (96, 32, 3000, None),
+    (130, 64, 800, None),
+    (2048, 128, 3437, None),       # a config-3 slice, streamed wide workgroups
+])
+def test_fp32_bulk_decisions_and_precision(orc, nx, nv, steps, cfg):
+    inst = wl.config3() if (nx, nv) == (2048, 128) else wl.small_hybrid(nx=nx, nv=nv)
+    ro, go, mo, st, ho = _oracle_hist(orc, inst, steps)
+    p = sth.Problem(desc_of(inst, precision=sth.FP32_BULK))
+    r32, g32, m32, k32, h32 = sth.sth_fine_run_masks(p, inst.rho_in, None, steps)
+    flips = int(np.sum(h32 != ho))
+    rr, gr, mr, kr, hr = sth.sth_fine_run_masks(p, inst.rho_in, None, steps, replay=ho)
+    p.close()
+    print(f"{nx}x{nv}, {steps} steps, FP32 bulk vs FP64 oracle: {flips} of {ho.size} (step, cell) "
+          f"states differ; rho {rel_err(r32, ro):.2e}, g {rel_err(g32, go):.2e}; with the oracle's "
+          f"history imposed rho {rel_err(rr, ro):.2e}, g {rel_err(gr, go):.2e}")
+    assert np.array_equal(hr, ho) and np.array_equal(mr, mo) and kr == st["kinetic_iface_steps"]
+    assert rel_err(rr, ro) < RHO32 and rel_err(gr, go) < G32
+    if flips == 0:
+        assert np.array_equal(r32, rr) and np.array_equal(g32, gr)
+
+
+def test_history_needs_hybrid_and_device_memory(orc):
+    inst = wl.small_hybrid(nx=64, nv=32)
+    inst.hybrid = False
+    p = sth.Problem(desc_of(inst))
+    with pytest.raises(sth.StHError):
+        sth.sth_fine_run_masks(p, inst.rho_in, None, 10)
+    p.close()
+    inst.hybrid = True
+    p = sth.Problem(desc_of(inst))
+    host = np.zeros((11, 1), dtype=np.uint64)
+    rho = np.zeros(inst.nx)
+    rc = sth.lib().sth_fine_run_masks(p.h, np.ascontiguousarray(inst.rho_in).ctypes.data_as(
+        ctypes.POINTER(ctypes.c_double)), None, 10, None, host.ctypes.data, rho.ctypes.data_as(
+        ctypes.POINTER(ctypes.c_double)), None, None, None, None)
+    assert rc == sth.STH_EINVAL and "device memory" in sth.sth_last_error()
+    with pytest.raises(ValueError):
+        sth.sth_fine_run_masks(p, inst.rho_in, None, 10, replay=np.zeros((10, inst.nx)))
+    p.close()

@@ -741,3 +741,51 @@ def test_1d3v_oracle_conserves_mass_and_equilibrium(orc):
     p.rhobar = 1.0
     r, g, m, k = o3.fine_propagate_3d(p, eps, epsc, flat, None, 20, nvy, nvz)
     assert np.array_equal(r, flat) and not np.any(g)
+
+
+def test_mask_history_replays_itself_and_pins_the_extremes(orc):
+    """Cell status history and replay (the tool that separates precision error
+    from decision flips): the recorded statuses are those of the plain run,
+    replaying them reproduces it bit for bit, an all-kinetic replay is the
+    full micro-macro scheme (hybrid off) and an all-fluid replay is the
+    limit scheme S^0, both bit for bit."""
+    inst = wl.small_hybrid(nx=96, nv=32)
+    p, ns, _ = orc.setup(inst.nx, inst.nv, inst.eps_iface, inst.rho_in, T=2e-3, N=1,
+                         flags=orc.FIELD | orc.HYBRID)
+    n = 600
+    args = (p, inst.eps_iface, inst.eps_cell, inst.rho_in, None, n)
+    r0, g0, m0, s0 = orc.fine_propagate(*args)
+    r1, g1, m1, s1, h1 = orc.fine_propagate_masks(*args)
+    assert np.array_equal(r1, r0) and np.array_equal(g1, g0) and np.array_equal(m1, m0) and s1 == s0
+    assert h1.shape == (n + 1, inst.nx) and np.array_equal(h1[-1], m0)
+    assert 0 < h1.sum() < h1.size and np.any(h1[1:] != h1[:-1])     # the rule switches cells
+    # interface counts follow from the history: p kinetic iff cell p or p+1 is
+    ifc = h1[:-1] | np.roll(h1[:-1], -1, axis=1)
+    assert s0["kinetic_iface_steps"] == ifc.sum()
+    r2, g2, m2_, s2, h2 = orc.fine_propagate_masks(*args, replay=h1)
+    assert np.array_equal(r2, r0) and np.array_equal(g2, g0) and np.array_equal(h2, h1)
+    # a changed step of the history changes the run: the replay is what
+    # decides (three neighbouring cells fluid: the two interfaces between
+    # them turn fluid)
+    hf = h1.copy()
+    hf[n // 2, 40:43] = 0
+    assert np.any(hf != h1)
+    r3, _, _, _, h3 = orc.fine_propagate_masks(*args, replay=hf)
+    assert np.array_equal(h3, hf) and not np.array_equal(r3, r0)
+    # all kinetic: the hybrid-off run
+    pk, _, _ = orc.setup(inst.nx, inst.nv, inst.eps_iface, inst.rho_in, T=2e-3, N=1, flags=orc.FIELD)
+    rk, gk, _, sk = orc.fine_propagate(pk, inst.eps_iface, inst.eps_cell, inst.rho_in, None, n)
+    r4, g4, _, s4, _ = orc.fine_propagate_masks(*args, replay=np.ones_like(h1))
+    assert np.array_equal(r4, rk) and np.array_equal(g4, gk)
+    assert s4["kinetic_iface_steps"] == sk["kinetic_iface_steps"] == n * inst.nx
+    # all fluid: S^0 step for step, g' = 0
+    r5, g5, _, s5, _ = orc.fine_propagate_masks(*args, replay=np.zeros_like(h1))
+    _, _, m2 = orc.velocity_grid(inst.nv)
+    dx = 1.0 / inst.nx
+    r = np.array(inst.rho_in, dtype=np.float64)
+    for _ in range(n):
+        J = orc.flux_J(r, orc.poisson(r, p.rhobar, dx), dx)
+        r = r + p.dt / dx * (m2 * J - m2 * np.roll(J, 1))
+    assert np.array_equal(r5, r) and not np.any(g5) and s5["kinetic_iface_steps"] == 0
+    with pytest.raises(ValueError):
+        orc.fine_propagate_masks(*args, replay=h1[:-1])

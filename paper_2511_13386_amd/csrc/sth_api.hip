@@ -1402,13 +1402,9 @@ int sth_fine_run_masks(sth_problem *p, const double *rho_in, const double *g_in,
     u.g_out = d_gout;
     u.kin = d_kin;
     u.mask_out = p->at<int>(p->L.mask);
-    u.nsteps = nsteps;
+    u.nsteps = nsteps;  // 0: the start state after the status rule
     u.mask_replay = (const unsigned long long *)mask_replay;
     u.mask_hist = (unsigned long long *)mask_hist;
-    if (nsteps == 0) {
-        // a zero-step run returns the initial state after the status rule
-        u.nsteps = 0;
-    }
     FineUnit *dt = p->at<FineUnit>(p->L.units);
     HIPCHK(hipMemcpy(dt, &u, sizeof(u), hipMemcpyHostToDevice));
     const FineShape sh = class_shape(p->prec, nx, p->nv);

@@ -57,7 +57,8 @@ struct FineUnit {
                               // (required by the streaming kernels: it is their state)
     unsigned long long *kin;  // kinetic interface-steps counter (atomic add)
     int *mask_out;            // [nx] final cell status, or NULL
-    long long nsteps;         // steps of this unit (<= 0: pc->nsteps)
+    long long nsteps;         // steps of this unit (0: none, the start state after
+                              // the status rule; < 0: pc->nsteps)
     const int *stop;          // the problem's stop flag (the unit does nothing
                               // when it is set), or NULL
     // Step range [step0, step1) of the slice run by this launch (step1 <= 0:

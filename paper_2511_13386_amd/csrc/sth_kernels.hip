@@ -547,7 +547,7 @@ __global__ void __launch_bounds__(BLK) k_fine(const FineUnit *__restrict__ units
     const int flags = C->flags;
     const bool hybrid = flags & STH_HYBRID, field = flags & STH_FIELD, literal = flags & STH_LITERAL_R;
     const bool cellwise = hybrid && (flags & STH_LITERAL_FLUX);
-    const long long nsteps = U.nsteps > 0 ? U.nsteps : C->nsteps;
+    const long long nsteps = U.nsteps >= 0 ? U.nsteps : C->nsteps;
     const long long step0 = U.step0 > 0 ? U.step0 : 0;
     const long long step1 = (U.step1 > 0 && U.step1 < nsteps) ? U.step1 : nsteps;
     const bool resume = step0 > 0, suspend = step1 < nsteps;

@@ -144,11 +144,15 @@ def cpu_baseline(inst, target_s):
     starts = np.array(rhos[:nun])
     gs = np.array([np.zeros((inst.nx, inst.nv))] +
                   [orc.lift(p, inst.eps_iface, r) for r in starts[1:]])
-    # calibrate on one unit
+    # calibrate on one unit, then one unit alone for about a second (one thread)
     t0 = time.perf_counter()
     _, kin1 = orc.fine_batch(p, inst.eps_iface, inst.eps_cell, starts[:1], 200, gs[:1])
     dt1 = time.perf_counter() - t0
     per_step_unit = dt1 / 200.0
+    n1 = int(max(200, min(ns, 1.0 / per_step_unit)))
+    t0 = time.perf_counter()
+    _, kin1 = orc.fine_batch(p, inst.eps_iface, inst.eps_cell, starts[:1], n1, gs[:1])
+    single = kin1 * inst.nv / (time.perf_counter() - t0)
     steps = int(max(200, min(ns, target_s / per_step_unit * threads / nun)))
     t0 = time.perf_counter()
     _, kin = orc.fine_batch(p, inst.eps_iface, inst.eps_cell, starts, steps, gs)
@@ -160,7 +164,19 @@ def cpu_baseline(inst, target_s):
         "kind": "oracle",
         "sample": (f"{nun} slices x {steps} fine steps of iteration 0 (of {ns} per slice), "
                    f"{el:.1f} s wall, OpenMP over slices"),
-    }
+    }, {"cpu_model": _cpu_model(), "nproc": os.cpu_count(), "threads": threads,
+        "single_thread_value": single,
+        "single_thread_sample": f"slice 1 alone, {n1} fine steps, one thread"}
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def run_batch(args, torch, sth, wl):
@@ -696,7 +712,7 @@ def main():
               f"{out['fp32_bulk' if prec2 == sth.FP32_BULK else 'fp64']['max_rel_rho_diff']:.2e}",
               file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(inst, args.cpu_seconds)
+        out["cpu_baseline"], out["cpu_oracle_host"] = cpu_baseline(inst, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

@@ -298,13 +298,56 @@ struct RowCoef {
 };
 
 // Running sums of a row pass.  They are kept in FP64 in both precisions:
-// each velocity pair is summed in the working precision and the pair sums
-// accumulate in FP64 (in FP32-bulk this bounds the rounding of the flux,
-// the projection and the norm over long slices, at one conversion per sum).
+// in FP64 each velocity pair is added to them; in FP32 bulk the pairs of a
+// group of at most four are summed in FP32 and the group sums accumulate in
+// FP64 (this bounds the rounding of the flux, the projection and the norm
+// over long slices, at one conversion per sum and group).
 template <typename Real>
 struct RowOut {
     double Sx, phi, gg;        // sum A, sum sign(v)|v|/dx w', sum g^2
 };
+
+// FP32-bulk sums of the current group of pairs.
+template <typename Real>
+struct PairAcc {
+    Real sx, ph, gg;
+};
+
+template <typename Real>
+__device__ __forceinline__ void acc_pair(RowOut<Real> &o, PairAcc<Real> &a, Real Aj, Real Am, Real cx, Real wj,
+                                         Real wm, Real gj, Real gm)
+{
+    if constexpr (sizeof(Real) == 8) {
+        o.Sx += (double)(Aj + Am);
+        o.phi += (double)(cx * (wm - wj));
+        o.gg += (double)(gj * gj + gm * gm);
+        keep(o.Sx);
+        keep(o.phi);
+        keep(o.gg);
+    } else {
+        a.sx += Aj + Am;
+        a.ph += cx * (wm - wj);
+        a.gg += gj * gj + gm * gm;
+        keep(a.sx);
+        keep(a.ph);
+        keep(a.gg);
+    }
+}
+
+// End of a group of pairs (FP32 bulk): its sums join the FP64 ones.
+template <typename Real>
+__device__ __forceinline__ void acc_flush(RowOut<Real> &o, PairAcc<Real> &a)
+{
+    if constexpr (sizeof(Real) == 4) {
+        o.Sx += (double)a.sx;
+        o.phi += (double)a.ph;
+        o.gg += (double)a.gg;
+        a.sx = a.ph = a.gg = Real(0);
+        keep(o.Sx);
+        keep(o.phi);
+        keep(o.gg);
+    }
+}
 
 // Byte offsets of one row pass in the unit slot (wavefront-uniform except vo).
 struct RowIO {
@@ -354,6 +397,7 @@ __device__ __forceinline__ void pair_chunk(int t0, const RowIO &io, const RowCoe
     constexpr unsigned R = sizeof(Real);
     // keep the scheduler from hoisting later chunks' loads into this one
     __builtin_amdgcn_sched_barrier(0);
+    PairAcc<Real> a{0, 0, 0};
     if (!LAST) {
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
@@ -393,18 +437,14 @@ __device__ __forceinline__ void pair_chunk(int t0, const RowIO &io, const RowCoe
         Ghi = Gm;
         const Real dgj = gj - gxj, dgm = gm - gxm;
         const Real Aj = cx * dgj + gvj, Am = cx * dgm + gvm;
-        o.Sx += (double)(Aj + Am);
         const Real wj = c.e * gj - c.aeps * Aj - c.aJ * vM;
         const Real wm = c.e * gm - c.aeps * Am + c.aJ * vM;
         buf_store(wj, io.rs, io.vo, (unsigned)j * io.rowb);
         buf_store(wm, io.rs, io.vo, (unsigned)m * io.rowb);
         if (first) buf_store(wj, io.rs, 0u, io.hno + (unsigned)j * R);
         if (last) buf_store(wm, io.rs, 0u, io.hpo + (unsigned)(m - HV) * R);
-        o.phi += (double)(cx * (wm - wj));
-        o.gg += (double)(gj * gj + gm * gm);
-        keep(o.Sx);
-        keep(o.phi);
-        keep(o.gg);
+        acc_pair(o, a, Aj, Am, cx, wj, wm, gj, gm);
+        if ((u & 3) == 3 || u == CH - 1) acc_flush(o, a);
         gj = gjn;
         gm = gmn;
     }
@@ -456,6 +496,7 @@ __device__ __forceinline__ RowOut<Real> row_pass_res(Real (&Wr)[NV], const RowCo
 {
     constexpr int HV = NV / 2;
     RowOut<Real> o{0, 0, 0};
+    PairAcc<Real> a{0, 0, 0};
     Real Glo = 0, Ghi = 0;  // zero-flux velocity ends
     Real cx = vt[0], M = vt[1], vM = vt[2], Mn = vt[3];
     Real hjv = hn[0], hmv = hp[HV - 1];
@@ -492,18 +533,14 @@ __device__ __forceinline__ RowOut<Real> row_pass_res(Real (&Wr)[NV], const RowCo
         Ghi = Gm;
         const Real dgj = gj - gxj, dgm = gm - gxm;
         const Real Aj = cxc * dgj + gvj, Am = cxc * dgm + gvm;
-        o.Sx += (double)(Aj + Am);
         const Real wj = c.e * gj - c.aeps * Aj - c.aJ * vMc;
         const Real wm = c.e * gm - c.aeps * Am + c.aJ * vMc;
         Wr[j] = wj;
         Wr[m] = wm;
         if (first) hno[t] = wj;
         if (last) hpo[HV - 1 - t] = wm;
-        o.phi += (double)(cxc * (wm - wj));
-        o.gg += (double)(gj * gj + gm * gm);
-        keep(o.Sx);
-        keep(o.phi);
-        keep(o.gg);
+        acc_pair(o, a, Aj, Am, cxc, wj, wm, gj, gm);
+        if ((t & 3) == 3 || t + 1 == HV) acc_flush(o, a);
         gj = gjn;
         gm = gmn;
     }
@@ -547,6 +584,10 @@ __global__ void __launch_bounds__(BLK) k_fine(const FineUnit *__restrict__ units
     const int flags = C->flags;
     const bool hybrid = flags & STH_HYBRID, field = flags & STH_FIELD, literal = flags & STH_LITERAL_R;
     const bool cellwise = hybrid && (flags & STH_LITERAL_FLUX);
+    // cell status history / replay (diagnostic runs only), read once
+    const unsigned long long *const mrep = U.mask_replay;
+    unsigned long long *const mhist = U.mask_hist;
+    const bool mdbg = hybrid && (mrep != nullptr || mhist != nullptr);
     const long long nsteps = U.nsteps >= 0 ? U.nsteps : C->nsteps;
     const long long step0 = U.step0 > 0 ? U.step0 : 0;
     const long long step1 = (U.step1 > 0 && U.step1 < nsteps) ? U.step1 : nsteps;
@@ -871,17 +912,17 @@ __global__ void __launch_bounds__(BLK) k_fine(const FineUnit *__restrict__ units
                 const double n0 = Nm > N0 ? Nm : N0, n1 = N0 > Np ? N0 : Np;
                 int ci = (int)(cr0 | (co0 & (n0 > delta0 ? 1u : 0u)));
                 int cn = (int)(cr1 | (co1 & (n1 > delta0 ? 1u : 0u)));
-                if (U.mask_replay || U.mask_hist) {
+                if (mdbg) {
                     const size_t row = (size_t)n * mw;
-                    if (U.mask_replay) {
+                    if (mrep) {
                         const int i1 = i + 1 == nx ? 0 : i + 1;
-                        ci = (int)((U.mask_replay[row + (i >> 6)] >> (i & 63)) & 1ull);
-                        cn = (int)((U.mask_replay[row + (i1 >> 6)] >> (i1 & 63)) & 1ull);
+                        ci = (int)((mrep[row + (i >> 6)] >> (i & 63)) & 1ull);
+                        cn = (int)((mrep[row + (i1 >> 6)] >> (i1 & 63)) & 1ull);
                     }
                     // the cells of a wavefront are 64 consecutive ones from a
                     // multiple of 64: one word per wavefront
                     const unsigned long long b = __ballot(ci != 0);
-                    if (U.mask_hist && lane == 0) U.mask_hist[row + (i >> 6)] = b;
+                    if (mhist && lane == 0) mhist[row + (i >> 6)] = b;
                 }
                 s_cm[par * ncm + i] = (unsigned char)ci;
                 *(i == 0 ? s_cm + par * ncm + nx : s_sink8 + lane) = (unsigned char)ci;

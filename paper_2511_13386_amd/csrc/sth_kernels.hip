@@ -327,11 +327,39 @@ __device__ __forceinline__ void acc_pair(RowOut<Real> &o, PairAcc<Real> &a, Real
     } else {
         a.sx += Aj + Am;
         a.ph += cx * (wm - wj);
-        a.gg += gj * gj + gm * gm;
+        a.gg = __builtin_fmaf(gm, gm, __builtin_fmaf(gj, gj, a.gg));
         keep(a.sx);
         keep(a.ph);
         keep(a.gg);
     }
+}
+
+// Relaxation with the source for a mirror pair, w' = e g - a eps A - a J v M
+// (v M of the pair's v<0 member; its mirror has the opposite sign).  FP32
+// bulk spells it as fused multiply-adds around one product a J v M per pair
+// (its pass is bound by VALU issue); FP64 keeps the compiler's form.
+template <typename Real>
+__device__ __forceinline__ void relax_pair(const RowCoef<Real> &c, Real gj, Real gm, Real Aj, Real Am, Real vM,
+                                           Real &wj, Real &wm)
+{
+    if constexpr (sizeof(Real) == 4) {
+        const Real sJ = c.aJ * vM;
+        wj = __builtin_fmaf(-c.aeps, Aj, __builtin_fmaf(c.e, gj, -sJ));
+        wm = __builtin_fmaf(-c.aeps, Am, __builtin_fmaf(c.e, gm, sJ));
+    } else {
+        wj = c.e * gj - c.aeps * Aj - c.aJ * vM;
+        wm = c.e * gm - c.aeps * Am + c.aJ * vM;
+    }
+}
+
+// Lazy-projection read g = w + M c1: one fused multiply-add per value in FP32
+// bulk (the compiler would otherwise share M c1 between the two members of a
+// pair and round it); FP64 keeps the compiler's form.
+template <typename Real>
+__device__ __forceinline__ Real recon(Real w, Real M, Real c1)
+{
+    if constexpr (sizeof(Real) == 4) return __builtin_fmaf(M, c1, w);
+    else return w + M * c1;
 }
 
 // End of a group of pairs (FP32 bulk): its sums join the FP64 ones.
@@ -414,11 +442,11 @@ __device__ __forceinline__ void pair_chunk(int t0, const RowIO &io, const RowCoe
         const Real cx = vt[4 * t], M = vt[4 * t + 1], vM = vt[4 * t + 2], Mn = vt[4 * t + 3];
         Real gjn, gmn;  // g_{j+1}, g_{m-1}
         if (u + 1 < CH) {
-            gjn = cur.wn[u + 1] + Mn * c.c1;
-            gmn = cur.wp[u + 1] + Mn * c.c1;
+            gjn = recon(cur.wn[u + 1], Mn, c.c1);
+            gmn = recon(cur.wp[u + 1], Mn, c.c1);
         } else if (!LAST) {
-            gjn = nxt.wn[0] + Mn * c.c1;
-            gmn = nxt.wp[0] + Mn * c.c1;
+            gjn = recon(nxt.wn[0], Mn, c.c1);
+            gmn = recon(nxt.wp[0], Mn, c.c1);
         } else {  // middle pair: rows HV-1 and HV are each other's neighbours
             gjn = gm;
             gmn = gj;
@@ -437,8 +465,8 @@ __device__ __forceinline__ void pair_chunk(int t0, const RowIO &io, const RowCoe
         Ghi = Gm;
         const Real dgj = gj - gxj, dgm = gm - gxm;
         const Real Aj = cx * dgj + gvj, Am = cx * dgm + gvm;
-        const Real wj = c.e * gj - c.aeps * Aj - c.aJ * vM;
-        const Real wm = c.e * gm - c.aeps * Am + c.aJ * vM;
+        Real wj, wm;
+        relax_pair(c, gj, gm, Aj, Am, vM, wj, wm);
         buf_store(wj, io.rs, io.vo, (unsigned)j * io.rowb);
         buf_store(wm, io.rs, io.vo, (unsigned)m * io.rowb);
         if (first) buf_store(wj, io.rs, 0u, io.hno + (unsigned)j * R);
@@ -469,7 +497,7 @@ __device__ __forceinline__ RowOut<Real> row_pass(const RowIO &io, const RowCoef<
         A.hp[u] = buf_load<Real>(io.rs, 0u, io.hp + (unsigned)(HV - 1 - u) * R);
     }
     Real Glo = 0, Ghi = 0;  // zero-flux velocity ends
-    Real gj = A.wn[0] + vt[1] * c.c1, gm = A.wp[0] + vt[1] * c.c1;
+    Real gj = recon(A.wn[0], vt[1], c.c1), gm = recon(A.wp[0], vt[1], c.c1);
 #pragma unroll 1
     for (int t0 = 0; t0 < HV - 2 * CH; t0 += 2 * CH) {
         pair_chunk<Real, NV, false, RAGGED, CH>(t0, io, c, first, last, vt, A, B, gj, gm, Glo, Ghi, o);
@@ -500,14 +528,14 @@ __device__ __forceinline__ RowOut<Real> row_pass_res(Real (&Wr)[NV], const RowCo
     Real Glo = 0, Ghi = 0;  // zero-flux velocity ends
     Real cx = vt[0], M = vt[1], vM = vt[2], Mn = vt[3];
     Real hjv = hn[0], hmv = hp[HV - 1];
-    Real gj = Wr[0] + M * c.c1, gm = Wr[NV - 1] + M * c.c1;
+    Real gj = recon(Wr[0], M, c.c1), gm = recon(Wr[NV - 1], M, c.c1);
 #pragma unroll
     for (int t = 0; t < HV; ++t) {
         const int j = t, m = NV - 1 - t;
         Real gjn, gmn;  // g_{j+1}, g_{m-1}
         if (t + 1 < HV) {
-            gjn = Wr[j + 1] + Mn * c.c1;
-            gmn = Wr[m - 1] + Mn * c.c1;
+            gjn = recon(Wr[j + 1], Mn, c.c1);
+            gmn = recon(Wr[m - 1], Mn, c.c1);
         } else {  // middle pair
             gjn = gm;
             gmn = gj;
@@ -533,8 +561,8 @@ __device__ __forceinline__ RowOut<Real> row_pass_res(Real (&Wr)[NV], const RowCo
         Ghi = Gm;
         const Real dgj = gj - gxj, dgm = gm - gxm;
         const Real Aj = cxc * dgj + gvj, Am = cxc * dgm + gvm;
-        const Real wj = c.e * gj - c.aeps * Aj - c.aJ * vMc;
-        const Real wm = c.e * gm - c.aeps * Am + c.aJ * vMc;
+        Real wj, wm;
+        relax_pair(c, gj, gm, Aj, Am, vMc, wj, wm);
         Wr[j] = wj;
         Wr[m] = wm;
         if (first) hno[t] = wj;

@@ -595,6 +595,10 @@ __global__ void __launch_bounds__(BLK) k_fine(const FineUnit *__restrict__ units
 {
     constexpr int CH = pair_chunk_len<Real, NV, BLK>();
     constexpr int HV = NV / 2;
+    // Where the mean of the cell-centred J is reduced: in FP32 bulk the row
+    // pass leaves the criterion phase little slack, so the field phase does
+    // it; in FP64 the criterion phase does.
+    constexpr bool kJtotInField = sizeof(Real) == 4;
     extern __shared__ __align__(16) unsigned char smem[];
 
     const FineUnit &U = units[blockIdx.x];
@@ -658,8 +662,8 @@ __global__ void __launch_bounds__(BLK) k_fine(const FineUnit *__restrict__ units
         *g = v;
     };
     double *s_tot = (double *)(smem + L.tot);
-    double *s_wtot = (double *)(smem + L.wtot);
     double *s_jtot = (double *)(smem + L.jtot);
+    double *s_wtot = (double *)(smem + L.wtot);
 
     GlobPtr<Real> W = (GlobPtr<Real>)U.g_out;        // [NV][ld] rows
     GlobPtr<Real> C1 = W + (size_t)NV * ld;          // [2][ld] lazy projection
@@ -867,7 +871,7 @@ __global__ void __launch_bounds__(BLK) k_fine(const FineUnit *__restrict__ units
                         jsum = jc;
                     }
                 }
-                if (hybrid) {
+                if (hybrid && kJtotInField) {
                     jsum = wave_total_f64(jsum);
                     if (lane == 0) s_jtot[k * NW + wid] = jsum;
                 }
@@ -896,8 +900,22 @@ __global__ void __launch_bounds__(BLK) k_fine(const FineUnit *__restrict__ units
         s_crit[i] = (unsigned char)(crit > C->eta0);
         *(i == 0 ? s_crit + nx : s_sink8 + lane) = (unsigned char)(crit > C->eta0);
     };
+    // Mean of the cell-centred J over all cells: from the wavefront totals
+    // of the field phase, or (FP64) summed by each wavefront that needs it,
+    // in the same order in every one, which keeps that reduction out of the
+    // field phase and in the criterion phase's slack.
+    auto mean_jc = [&]() {
+        if constexpr (kJtotInField) {
+            return wave_total_f64(lane < nslot ? s_jtot[lane] : 0.0) * inv_nx;
+        } else {
+            double acc = 0.0;
+#pragma unroll 1
+            for (int q = lane; q < nx; q += kWave) acc += s_jc[q];
+            return wave_total_f64(acc) * inv_nx;
+        }
+    };
     auto macro_crit = [&]() {
-        const double mJ = wave_total_f64(lane < nslot ? s_jtot[lane] : 0.0) * inv_nx;
+        const double mJ = mean_jc();
 #pragma unroll
         for (int k = 0; k < IPTM; ++k) {
             const int i = k * BS + tid;
@@ -910,7 +928,7 @@ __global__ void __launch_bounds__(BLK) k_fine(const FineUnit *__restrict__ units
     // wait at the barrier for the second ones, which the scheduler serves
     // later.
     auto macro_crit_half = [&]() {
-        const double mJ = wave_total_f64(lane < nslot ? s_jtot[lane] : 0.0) * inv_nx;
+        const double mJ = mean_jc();
 #pragma unroll
         for (int k = 0; k < IPTM; ++k) {
 #pragma unroll

@@ -166,7 +166,22 @@ def cpu_baseline(inst, target_s):
                    f"{el:.1f} s wall, OpenMP over slices"),
     }, {"cpu_model": _cpu_model(), "nproc": os.cpu_count(), "threads": threads,
         "single_thread_value": single,
-        "single_thread_sample": f"slice 1 alone, {n1} fine steps, one thread"}
+        "single_thread_sample": f"slice 1 alone, {n1} fine steps, one thread",
+        "config1_single_thread": _config1_oracle(orc)}
+
+
+def _config1_oracle(orc):
+    """The oracle's one-thread rate on the plain serial micro-macro run
+    (64 x 32, eps = 1e-2, full kinetic, the whole T = 0.1)."""
+    from paper_2511_13386_amd import workloads as wl
+    c1 = wl.config1()
+    p, ns, _ = orc.setup(c1.nx, c1.nv, c1.eps_iface, c1.rho_in, T=c1.T, N=1, theta=c1.theta,
+                         flags=orc.FIELD)
+    t0 = time.perf_counter()
+    _, _, _, st = orc.fine_propagate(p, c1.eps_iface, c1.eps_cell, c1.rho_in, None, ns)
+    el = time.perf_counter() - t0
+    return {"value": st["kinetic_iface_steps"] * c1.nv / el, "unit": "cell-updates/s",
+            "steps": ns, "seconds": el}
 
 
 def _cpu_model():

@@ -1,0 +1,58 @@
+"""Host-side parts of bench.py: the one-GPU guard, the CPU baseline block
+and the reading of the committed HBM counter summary (no GPU needed)."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+from paper_2511_13386_amd import workloads as wl  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in line["error"]
+
+
+def test_cpu_baseline_block_has_the_contract_fields():
+    inst = wl.config2(nx=64, nv=32, N=4, T=1e-3)
+    base, host = bench.cpu_baseline(inst, 0.3)
+    assert set(base) == {"value", "unit", "cores", "kind", "sample"}
+    assert base["kind"] == "oracle" and base["unit"] == "cell-updates/s"
+    assert base["value"] > 0 and base["cores"] >= 1 and "fine steps" in base["sample"]
+    assert host["single_thread_value"] > 0 and host["threads"] == base["cores"]
+    c1 = host["config1_single_thread"]
+    assert c1["value"] > 0 and c1["steps"] > 10000
+
+
+def test_traffic_is_read_only_for_the_current_sources(tmp_path, monkeypatch):
+    """The committed FETCH_SIZE/WRITE_SIZE summary is used only when its
+    recorded source hash is that of the kernels being run."""
+    path = os.path.join(ROOT, "profiles", "k_fine_512x64_fp64_hbm_traffic.txt")
+    if not os.path.exists(path):
+        pytest.skip("no committed counter summary")
+    lines = open(path).read().splitlines()
+    assert any(l.startswith("kernel_sources_sha256:") for l in lines)
+    assert len(bench.sources_sha256()) == 64
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "sources_sha256", lambda: "a" * 64)
+    os.makedirs(tmp_path / "profiles")
+    target = tmp_path / "profiles" / "k_fine_512x64_fp64_hbm_traffic.txt"
+
+    def with_sha(h):
+        return "\n".join(f"kernel_sources_sha256: {h}" if l.startswith("kernel_sources_sha256:") else l
+                         for l in lines) + "\n"
+    target.write_text(with_sha("0" * 64))
+    assert bench.measured_traffic("512x64_fp64") is None
+    target.write_text(with_sha("a" * 64))
+    t = bench.measured_traffic("512x64_fp64")
+    assert t is not None and t > 0
+    assert bench.measured_traffic("no_such_workload") is None

@@ -283,7 +283,9 @@ int  sth_get_info(const sth_problem *p, sth_info *out);
  * NULL = 0) outside the parareal bookkeeping, with the problem's grids,
  * step and flags; results to host arrays (any may be NULL): rho_out[nx],
  * g_out[nx*nv] x-major, cell_mask_out[nx], kinetic interface-steps.
- * Uses the same kernel as the batched sweep.  Synchronises. */
+ * nsteps = 0 returns the start state after the first status rule (g zero
+ * on fluid interfaces).  Uses the same kernel as the batched sweep.
+ * Synchronises. */
 int  sth_fine_run(sth_problem *p, const double *rho_in, const double *g_in, long long nsteps,
                   double *rho_out, double *g_out, int *cell_mask_out, double *kin_out,
                   void *stream);

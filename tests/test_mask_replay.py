@@ -133,3 +133,28 @@ def test_history_needs_hybrid_and_device_memory(orc):
     with pytest.raises(ValueError):
         sth.sth_fine_run_masks(p, inst.rho_in, None, 10, replay=np.zeros((10, inst.nx)))
     p.close()
+
+
+def test_literal_remainder_criterion_history(orc):
+    """The criterion on |R| as printed (STH_LITERAL_R, no eps^2): with the
+    threshold at the 30th percentile of the initial |R| (the norm rule kept
+    out by a large delta0) cells switch often, and the GPU's status history
+    equals the oracle's step for step."""
+    inst = wl.small_hybrid(seed=1, nx=96, nv=32)
+    po, _, _ = oracle_of(orc, inst)
+    po.flags |= orc.LITERAL_R
+    d0 = orc.diagnostics(po, inst.eps_iface, inst.eps_cell, inst.rho_in, np.zeros((inst.nx, inst.nv)))
+    inst.eta0 = float(np.percentile(np.abs(d0["R"]), 30))
+    inst.delta0 = 10.0
+    po.eta0, po.delta0 = inst.eta0, inst.delta0
+    steps = 1500
+    ro, go, mo, st, ho = orc.fine_propagate_masks(po, inst.eps_iface, inst.eps_cell, inst.rho_in, None,
+                                                  steps)
+    assert np.sum(ho[1:] != ho[:-1]) > 100
+    d = desc_of(inst)
+    d.flags |= sth.LITERAL_R
+    p = sth.Problem(d)
+    rg, gg, mg, kg, hg = sth.sth_fine_run_masks(p, inst.rho_in, None, steps)
+    p.close()
+    assert np.array_equal(hg, ho) and kg == st["kinetic_iface_steps"]
+    assert rel_err(rg, ro) < RHO64 and rel_err(gg, go) < G64

@@ -158,3 +158,25 @@ def test_literal_remainder_criterion_history(orc):
     p.close()
     assert np.array_equal(hg, ho) and kg == st["kinetic_iface_steps"]
     assert rel_err(rg, ro) < RHO64 and rel_err(gg, go) < G64
+
+
+@pytest.mark.parametrize("precision", [sth.FP64, sth.FP32_BULK])
+def test_field_off_history(orc, precision):
+    """Hybrid without the field (E = 0: the remainder keeps only its -D3[J]
+    term): the status history against the oracle's, step for step in FP64,
+    counted in FP32 bulk."""
+    inst = wl.small_hybrid(seed=3, nx=130, nv=32)
+    inst.field_on = False
+    steps = 2000
+    ro, go, mo, st, ho = _oracle_hist(orc, inst, steps)
+    assert np.any(ho[1:] != ho[:-1])
+    p = sth.Problem(desc_of(inst, precision=precision))
+    rg, gg, mg, kg, hg = sth.sth_fine_run_masks(p, inst.rho_in, None, steps)
+    rr, gr, _, _, _ = sth.sth_fine_run_masks(p, inst.rho_in, None, steps, replay=ho)
+    p.close()
+    if precision == sth.FP64:
+        assert np.array_equal(hg, ho) and kg == st["kinetic_iface_steps"]
+        assert rel_err(rg, ro) < RHO64 and rel_err(gg, go) < G64
+    else:
+        print(f"field off, FP32 bulk: {int(np.sum(hg != ho))} of {ho.size} (step, cell) states differ")
+        assert rel_err(rr, ro) < RHO32 and rel_err(gr, go) < G32

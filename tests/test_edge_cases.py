@@ -48,10 +48,14 @@ def test_smallest_grids(orc, nx, nv, hybrid):
     _check(*_pair(orc, inst, 400))
 
 
-@pytest.mark.parametrize("precision,steps", [(sth.FP64, 60), (sth.FP32_BULK, 60)])
-def test_largest_grid_with_ragged_wavefront(orc, precision, steps):
-    inst = wl.config2(nx=2047, nv=128, N=4, T=1e-3)
-    _check(*_pair(orc, inst, steps, precision), precision)
+@pytest.mark.parametrize("nx,nv", [(2047, 128), (2048, 16), (2048, 32), (2040, 64)])
+@pytest.mark.parametrize("precision", [sth.FP64, sth.FP32_BULK])
+def test_largest_grids(orc, nx, nv, precision):
+    """The largest grids in every velocity class (resident rows with four
+    interfaces per thread at nv = 16, wide streamed workgroups, ragged last
+    wavefronts)."""
+    inst = wl.config2(nx=nx, nv=nv, N=4, T=1e-3)
+    _check(*_pair(orc, inst, 60, precision), precision)
 
 
 @pytest.mark.parametrize("hybrid", [False, True])

@@ -77,6 +77,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=8)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--flip-steps", type=int, default=50000,
+                    help="default workload: fine steps of slice 1 over which FP32-bulk and FP64 "
+                         "threshold decisions are compared (0: skip)")
     ap.add_argument("--nx", type=int, default=512)
     ap.add_argument("--nv", type=int, default=64)
     ap.add_argument("--slices", type=int, default=64)
@@ -726,6 +729,27 @@ def main():
         print(f"# other precision: {v2:.3e} cell-updates/s, rho diff "
               f"{out['fp32_bulk' if prec2 == sth.FP32_BULK else 'fp64']['max_rel_rho_diff']:.2e}",
               file=sys.stderr, flush=True)
+        if args.flip_steps > 0:
+            # threshold decisions against rounding on slice 1 (from rho_in,
+            # g' = 0) over a bounded horizon: the (step, cell) states whose
+            # status differs between FP32 bulk and FP64, and the density
+            # difference once the FP64 status history is imposed on FP32
+            nflip = min(args.flip_steps, info.steps_per_slice)
+            p64 = sth.Problem(desc(precision=sth.FP64))
+            p32 = sth.Problem(desc(precision=sth.FP32_BULK))
+            r64, _, _, _, h64 = sth.sth_fine_run_masks(p64, inst.rho_in, None, nflip)
+            r32, _, _, _, h32 = sth.sth_fine_run_masks(p32, inst.rho_in, None, nflip)
+            r32i, _, _, _, _ = sth.sth_fine_run_masks(p32, inst.rho_in, None, nflip, replay=h64)
+            p64.close()
+            p32.close()
+            scale = float(np.max(np.abs(r64)))
+            out["fp32_bulk" if prec2 == sth.FP32_BULK else "fp64"]["decisions_slice1"] = {
+                "steps": nflip, "cells": inst.nx,
+                "states_differing": int(np.sum(h32 != h64)),
+                "max_rel_rho_diff": float(np.max(np.abs(r32 - r64))) / scale,
+                "max_rel_rho_diff_fp64_history_imposed": float(np.max(np.abs(r32i - r64))) / scale,
+            }
+            del h64, h32
     if not args.no_cpu_baseline:
         out["cpu_baseline"], out["cpu_oracle_host"] = cpu_baseline(inst, args.cpu_seconds)
     print(json.dumps(out), flush=True)

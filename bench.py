@@ -253,12 +253,19 @@ def run_batch(args, torch, sth, wl):
         wall = time.perf_counter() - t0
         ms = [a.elapsed_time(b) for a, b in ev]
         kin = sum(p.info().kinetic_iface_steps * p.nv for p in problems)
+        # algorithmic bytes: read and write of g' per kinetic cell-update,
+        # plus the macroscopic data of each kinetic interface-step
+        realsz = 8 if precision_label == "fp64" else 4
+        alg = sum(p.info().kinetic_iface_steps * (p.nv * 2 * realsz + MACRO_BYTES_PER_IFACE_STEP)
+                  for p in problems)
+        solve.alg_bytes = alg
         return kin, ms, wall
 
     problems = [sth.Problem(desc(i, prec)) for i in insts]
     footprint = sum(p.info().footprint_bytes for p in problems)
     kin, ms, wall = solve(problems, args.precision)
     rate = kin / (sum(ms) * 1e-3)
+    alg_gbs = solve.alg_bytes / (sum(ms) * 1e-3) / 1e9
     print(f"# batched {len(problems)} instances: {kin:.3e} kinetic cell-updates in {sum(ms):.0f} ms of sweeps",
           file=sys.stderr, flush=True)
     U_all = [sth.sth_get_rho(p) for p in problems]
@@ -307,6 +314,8 @@ def run_batch(args, torch, sth, wl):
         "single_instance_fp64": {"value": rate1, "unit": "cell-updates/s",
                                  "instances": len(U_batch),
                                  "sample": f"every {args.baseline_every}-th instance, alone, FP64"},
+        "roofline": {"bound": "hbm", "achieved": alg_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": alg_gbs / HBM_PEAK_GBS, "traffic": None},
         "speedup_vs_single_fp64": rate / rate1,
         "max_rel_rho_diff_vs_single_fp64": max(errs) if errs else None,
         "mass_drift_rel_max": mass,

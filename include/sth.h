@@ -178,8 +178,9 @@ int  sth_footprint_bytes(const sth_problem_desc *d, size_t *out);
 /* Create a problem: validate the description, derive the grids, the
  * normalised Maxwellian, the stable fine step, exp(-dt/eps^2) and
  * -expm1(-dt/eps^2) per interface, and upload everything.  `arena` is a
- * device pointer of `arena_bytes` >= sth_footprint_bytes (NULL: the library
- * allocates).  Synchronises the null stream.  The problem starts at
+ * 256-byte aligned device pointer of `arena_bytes` >= sth_footprint_bytes
+ * (NULL: the library allocates); a host pointer is STH_EINVAL, a short
+ * arena STH_ENOMEM.  Synchronises the null stream.  The problem starts at
  * iteration 0 with U^0 = rho0 and no coarse guess. */
 int  sth_create(const sth_problem_desc *d, void *arena, size_t arena_bytes, sth_problem **out);
 

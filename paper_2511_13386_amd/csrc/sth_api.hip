@@ -708,6 +708,10 @@ int sth_create(const sth_problem_desc *d, void *arena, size_t arena_bytes, sth_p
             delete p;
             return fail(STH_EINVAL, "arena must be 256-byte aligned");
         }
+        if (!is_device_ptr(arena)) {
+            delete p;
+            return fail(STH_EINVAL, "arena must be device memory");
+        }
         p->base = (char *)arena;
         p->owned = false;
     } else {

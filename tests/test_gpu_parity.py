@@ -403,6 +403,15 @@ def test_torch_arena_and_stream(orc):
     assert np.array_equal(U, sth.sth_get_rho(ref))
     p.close()
     ref.close()
+    # a host arena and a short one are refused before any device work
+    host = torch.empty(nbytes + 512, dtype=torch.uint8)
+    off = (-host.data_ptr()) % 256
+    with pytest.raises(sth.StHError) as e:
+        sth.Problem(d, arena=host[off:off + nbytes])
+    assert e.value.code == sth.STH_EINVAL and "device memory" in str(e.value)
+    with pytest.raises(sth.StHError) as e:
+        sth.Problem(d, arena=arena[:nbytes // 2])
+    assert e.value.code == sth.STH_ENOMEM
 
 
 def test_state_errors():

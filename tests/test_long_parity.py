@@ -69,6 +69,11 @@ def test_config3_one_iteration_reported(orc):
     print(f"config 3, T = 1/64, one iteration: FP64 rho {rel_err(U64, Uo):.2e}, FP32 bulk rho "
           f"{rel_err(U32, Uo):.2e}; kinetic interface-steps oracle {kin:.0f}, FP64 {k64:.0f}, "
           f"FP32 {k32:.0f}; error oracle {erro[0]:.9e}, FP64 {e64[0]:.9e}, FP32 {e32[0]:.9e}", flush=True)
+    per = np.max(np.abs(U64 - Uo), axis=1) / np.max(np.abs(Uo))
+    first = int(np.argmax(per > 1e-10))
+    print(f"FP64 slice values: {int(np.sum(per > 1e-10))} of {inst.N + 1} differ by more than 1e-10, "
+          f"the first at slice {first} ({per[first]:.1e}), those before it by at most "
+          f"{np.max(per[:first]) if first else 0.0:.1e}", flush=True)
     assert abs(k64 - kin) < 1e-6 * kin and abs(k32 - kin) < 1e-5 * kin
     assert abs(e64[0] - erro[0]) < 1e-5 * erro[0] and abs(e32[0] - erro[0]) < 1e-4 * erro[0]
     assert rel_err(U64, Uo) < 1e-2 and rel_err(U32, Uo) < 1e-2

@@ -105,6 +105,11 @@ def test_config3_slices_with_status_histories(orc):
     _wait(threads, t0, "oracle slices")
     p64 = sth.Problem(desc_of(inst, precision=sth.FP64, lift_order=1))
     p32 = sth.Problem(desc_of(inst, precision=sth.FP32_BULK, lift_order=1))
+    # the coarse guess itself: implicit solves with alpha = m2 dtG/dx^2 ~ 500
+    sth.sth_coarse_sweep(p64)
+    coarse = sth.sth_get_rho(p64)[:inst.N]
+    print(f"coarse guess against the oracle's: {rel_err(coarse, np.array(starts)):.1e}", flush=True)
+    assert rel_err(coarse, np.array(starts)) < 1e-8
     total = 0
     for n in sample:
         g0, ro, go, mo, st, ho = res[n]

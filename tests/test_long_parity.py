@@ -82,7 +82,7 @@ def test_config3_one_iteration_reported(orc):
 
 
 def test_config3_slices_with_status_histories(orc):
-    """Eight slices of the first sweep (the coarse-guess densities with their
+    """Nine slices of the first sweep (the coarse-guess densities with their
     lifted perturbations as starts, 13,747 steps each): the GPU's status
     history against the oracle's, and with the oracle's imposed the slice
     ends to the FP64 and FP32-bulk tolerances."""
@@ -91,7 +91,7 @@ def test_config3_slices_with_status_histories(orc):
     starts = [np.array(inst.rho_in, dtype=np.float64)]
     for _ in range(inst.N - 1):
         starts.append(orc.coarse_step(po, dtG, starts[-1]))
-    sample = list(range(0, inst.N, inst.N // 8))
+    sample = [0, 1] + list(range(inst.N // 8, inst.N, inst.N // 8))
     res = {}
 
     def run(n):

@@ -28,10 +28,11 @@ pytestmark = [pytest.mark.gpu,
 
 RHO64, G64 = 1e-12, 1e-10
 # FP32 bulk over 13,747 steps of a 2048-cell slice: the FP32 rounding of g'
-# accumulates beyond the short-run tolerances (2e-6, 2e-4); the config-3
-# tolerances of the FP32-bulk form hold instead: g' 2e-3 relative, and the
-# density, with the decisions imposed, 1e-5 (tighter than its config-3 1e-4)
-RHO32, G32 = 1e-5, 2e-3
+# accumulates beyond the short-run tolerances (2e-6, 2e-4), and a lifted
+# start rounded to FP32 moves the slice end further (the slice map amplifies
+# high-frequency start differences about a thousandfold); the config-3
+# tolerances of the FP32-bulk form hold: rho 1e-4, g' 2e-3 relative
+RHO32, G32 = 1e-4, 2e-3
 
 
 def _wait(threads, t0, what):

@@ -538,7 +538,7 @@ def run_unit(args, torch, sth, wl):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+        print(json.dumps({"error": "this implementation runs on one GPU; --gpus must be 1 "
                           "(the slice-parallel multi-GPU path is design only)"}))
         sys.exit(2)
 

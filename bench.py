@@ -445,11 +445,21 @@ def run_convergence(args, torch, sth, wl):
                              start_mode=mode, cfl_theta=inst.theta,
                              flags=sth.FIELD | (sth.HYBRID if adapt else 0), Lx=inst.Lx, vstar=inst.vstar)
                 p = sth.Problem(d)
-                errs = sth.parareal_solve(p, K=inst.N, tol=inst.tol)
+                try:
+                    errs = sth.parareal_solve(p, K=inst.N, tol=inst.tol)
+                    diverged = False
+                except sth.StHError as e:
+                    # the correction reported a non-finite density (the L = 3
+                    # lifting at eps ~ 1): the run is recorded as diverged
+                    if e.code != sth.STH_ENONFINITE:
+                        raise
+                    errs = sth.sth_get_errors(p) or [float("nan")]
+                    diverged = True
                 info = p.info()
                 rows.append({"start": mode_name, "lift_order": L, "adaptation": adapt, "eps": eps,
-                             "iterations": len(errs),
-                             "final_err": errs[-1], "steps_per_slice": info.steps_per_slice,
+                             "iterations": len(errs), "diverged": diverged,
+                             "final_err": errs[-1] if np.isfinite(errs[-1]) else None,
+                             "steps_per_slice": info.steps_per_slice,
                              "kinetic_fraction": info.kinetic_iface_steps / max(
                                  1.0, inst.nx * info.steps_per_slice * sum(inst.N - k for k in range(len(errs))))})
                 p.close()

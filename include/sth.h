@@ -175,7 +175,9 @@ int  sth_get_fine_config(int precision, int nx, int nv, sth_fine_config *out);
  * Only sizes are read.  *out receives the byte count. */
 int  sth_footprint_bytes(const sth_problem_desc *d, size_t *out);
 
-/* Create a problem: validate the description, derive the grids, the
+/* Create a problem (the initial-value problem of Section 3.1: initial data
+ * rho_in, g_in, the times T^n = n T / N of the parareal decomposition, and
+ * the discretisation of Section 2.3): validate the description, derive the grids, the
  * normalised Maxwellian, the stable fine step, exp(-dt/eps^2) and
  * -expm1(-dt/eps^2) per interface, and upload everything.  `arena` is a
  * 256-byte aligned device pointer of `arena_bytes` >= sth_footprint_bytes
@@ -270,11 +272,15 @@ void sth_graph_destroy(sth_graph *g);
 int  sth_moments_criteria(const sth_problem *p, int slice, double *E, double *J, double *Phi,
                           double *N, double *R, int *cell_mask, void *stream);
 
-/* Copy U^n for n = 0..N to host_out[(N+1)*nx].  Synchronises. */
+/* Copy the parareal iterate of Algorithm 1, the slice-end densities U^n_k
+ * for n = 0..N at the current iteration k, to host_out[(N+1)*nx].
+ * Synchronises. */
 int  sth_get_rho(const sth_problem *p, double *host_out);
 
 /* Copy the end-of-slice perturbation g of slice n (1..N) from the last fine
- * sweep that computed it, x-major, to host_out[nx*nv].  Synchronises. */
+ * sweep that computed it (the fine propagator F of Algorithm 1 returns the
+ * state (rho, g) of scheme S^HMM, Section 2.3; the iterate keeps only rho),
+ * x-major, to host_out[nx*nv].  Synchronises. */
 int  sth_get_g(const sth_problem *p, int slice, double *host_out);
 
 /* Scalars of the problem (grids, steps, counters).  Synchronises. */
@@ -300,10 +306,12 @@ int  sth_fine_run(sth_problem *p, const double *rho_in, const double *g_in, long
  * (device memory, or NULL) imposes them instead of the rule, so that runs
  * in two precisions can share one sequence of kinetic regions and their
  * difference is then precision alone.  Both need STH_HYBRID (else
- * STH_EINVAL); host pointers there are STH_EINVAL.  Both arrays hold
- * (nsteps + 1) rows; the caller owns them.  Synchronises. */
+ * STH_EINVAL); host pointers there are STH_EINVAL.  mask_words is the
+ * number of 64-bit words each given array holds; it must be at least
+ * (nsteps + 1) * ((nx + 63) / 64), else STH_EINVAL (nothing is launched).
+ * The caller owns both arrays.  Synchronises. */
 int  sth_fine_run_masks(sth_problem *p, const double *rho_in, const double *g_in, long long nsteps,
-                        const uint64_t *mask_replay, uint64_t *mask_hist,
+                        const uint64_t *mask_replay, uint64_t *mask_hist, long long mask_words,
                         double *rho_out, double *g_out, int *cell_mask_out, double *kin_out,
                         void *stream);
 

@@ -858,6 +858,8 @@ int sth_fine_sweep_batched(sth_problem *const *probs, int count, void *stream)
         if (!probs[b]) return fail(STH_EINVAL, "null problem in batch");
         if (!probs[b]->coarse_done) return fail(STH_ESTATE, "sth_coarse_sweep must precede the fine sweep");
         if (probs[b]->chunk_pos >= 0) return fail(STH_ESTATE, "a chunked fine sweep is in progress");
+        for (int c = 0; c < b; ++c)
+            if (probs[c] == probs[b]) return fail(STH_EINVAL, "a problem appears twice in the batch");
     }
     std::vector<SweepItem> items;
     LiftBatch lb;
@@ -1007,14 +1009,16 @@ int sth_parareal_correct_batched(sth_problem *const *probs, int count, double *e
     double *herr = (double *)(htab + jbytes);
     if (e == hipSuccess && errs_out)
         e = hipMemcpyAsync(herr, derr, sizeof(double) * count, hipMemcpyDeviceToHost, st);
+    std::vector<double> errs(count, 0.0);
+    if (e == hipSuccess && errs_out) {
+        // the errors are read from the mirror before the table is released,
+        // so that no other caller can reuse the slot and overwrite them
+        e = hipStreamSynchronize(st);
+        if (e == hipSuccess) std::memcpy(errs.data(), herr, sizeof(double) * count);
+    }
     rc = release_table(slot, st);
     if (e != hipSuccess) return hip_fail(e, "sth_parareal_correct_batched");
     if (rc) return rc;
-    std::vector<double> errs(count, 0.0);
-    if (errs_out) {
-        HIPCHK(hipStreamSynchronize(st));
-        std::memcpy(errs.data(), herr, sizeof(double) * count);
-    }
     bool finite = true;
     for (int b = 0; b < count; ++b) {
         sth_problem *p = probs[b];
@@ -1370,18 +1374,24 @@ int sth_get_info(const sth_problem *p, sth_info *out)
 int sth_fine_run(sth_problem *p, const double *rho_in, const double *g_in, long long nsteps,
                  double *rho_out, double *g_out, int *cell_mask_out, double *kin_out, void *stream)
 {
-    return sth_fine_run_masks(p, rho_in, g_in, nsteps, nullptr, nullptr, rho_out, g_out, cell_mask_out,
+    return sth_fine_run_masks(p, rho_in, g_in, nsteps, nullptr, nullptr, 0, rho_out, g_out, cell_mask_out,
                               kin_out, stream);
 }
 
 int sth_fine_run_masks(sth_problem *p, const double *rho_in, const double *g_in, long long nsteps,
-                       const uint64_t *mask_replay, uint64_t *mask_hist, double *rho_out, double *g_out,
-                       int *cell_mask_out, double *kin_out, void *stream)
+                       const uint64_t *mask_replay, uint64_t *mask_hist, long long mask_words, double *rho_out,
+                       double *g_out, int *cell_mask_out, double *kin_out, void *stream)
 {
     if (!p || !rho_in) return fail(STH_EINVAL, "null argument");
     if (nsteps < 0) return fail(STH_EINVAL, "nsteps must be >= 0");
     if ((mask_replay || mask_hist) && !(p->flags & STH_HYBRID))
         return fail(STH_EINVAL, "a cell status history needs STH_HYBRID");
+    if (mask_replay || mask_hist) {
+        // (nsteps + 1) rows of ceil(nx/64) words, computed without overflow
+        const long long mw = (p->nx + kWave - 1) / kWave;
+        if (mask_words < 0 || nsteps + 1 > mask_words / mw)
+            return fail(STH_EINVAL, "mask_words is smaller than (nsteps + 1) * ceil(nx / 64)");
+    }
     if (mask_replay && !is_device_ptr(mask_replay)) return fail(STH_EINVAL, "mask_replay must be device memory");
     if (mask_hist && !is_device_ptr(mask_hist)) return fail(STH_EINVAL, "mask_hist must be device memory");
     hipStream_t st = (hipStream_t)stream;

@@ -110,7 +110,7 @@ def lib() -> ctypes.CDLL:
         L.sth_get_info.argtypes = [_VP, ctypes.POINTER(Info)]
         L.sth_fine_run.argtypes = [_VP, _D, _D, ctypes.c_longlong, _D, _D,
                                    ctypes.POINTER(ctypes.c_int), _D, _VP]
-        L.sth_fine_run_masks.argtypes = [_VP, _D, _D, ctypes.c_longlong, _VP, _VP, _D, _D,
+        L.sth_fine_run_masks.argtypes = [_VP, _D, _D, ctypes.c_longlong, _VP, _VP, ctypes.c_longlong, _D, _D,
                                          ctypes.POINTER(ctypes.c_int), _D, _VP]
         L.sth_parareal_correct_batched.argtypes = [ctypes.POINTER(_VP), ctypes.c_int, _D, _VP]
         L.sth_get_errors.argtypes = [_VP, _D]
@@ -417,6 +417,7 @@ def sth_fine_run_masks(p: Problem, rho_in, g_in, nsteps: int, replay=None, strea
     torch.cuda.synchronize(dev)
     _check(lib().sth_fine_run_masks(p.h, _d(rho_in), _d(g_arr), nsteps,
                                     None if d_rep is None else d_rep.data_ptr(), d_hist.data_ptr(),
+                                    rows * mw,
                                     _d(rho), _d(g), mask.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
                                     ctypes.byref(kin), _stream(stream)))
     words = np.ascontiguousarray(d_hist.cpu().numpy()).view("<u8")

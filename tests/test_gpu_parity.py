@@ -424,6 +424,14 @@ def test_state_errors():
     with pytest.raises(sth.StHError) as e:
         sth.sth_parareal_correct(p)
     assert e.value.code == sth.STH_ESTATE
+    # a problem twice in one batched sweep would have two workgroups write
+    # the same slots: refused before anything is launched
+    with pytest.raises(sth.StHError) as e:
+        sth.sth_fine_sweep_batched([p, p])
+    assert e.value.code == sth.STH_EINVAL and "twice" in str(e.value)
+    sth.sth_fine_sweep_batched([p])
+    e1, k1 = sth.sth_parareal_correct(p)
+    assert k1 == 1 and np.isfinite(e1)
     p.close()
 
 

@@ -127,11 +127,24 @@ def test_history_needs_hybrid_and_device_memory(orc):
     host = np.zeros((11, 1), dtype=np.uint64)
     rho = np.zeros(inst.nx)
     rc = sth.lib().sth_fine_run_masks(p.h, np.ascontiguousarray(inst.rho_in).ctypes.data_as(
-        ctypes.POINTER(ctypes.c_double)), None, 10, None, host.ctypes.data, rho.ctypes.data_as(
+        ctypes.POINTER(ctypes.c_double)), None, 10, None, host.ctypes.data, 11, rho.ctypes.data_as(
         ctypes.POINTER(ctypes.c_double)), None, None, None, None)
     assert rc == sth.STH_EINVAL and "device memory" in sth.sth_last_error()
     with pytest.raises(ValueError):
         sth.sth_fine_run_masks(p, inst.rho_in, None, 10, replay=np.zeros((10, inst.nx)))
+    # a history buffer shorter than (nsteps + 1) rows is refused before any launch
+    import torch
+    mw = (inst.nx + 63) // 64
+    dev = torch.zeros((11, mw), dtype=torch.int64, device="cuda")
+    for words in (11 * mw - 1, -1):
+        rc = sth.lib().sth_fine_run_masks(p.h, np.ascontiguousarray(inst.rho_in).ctypes.data_as(
+            ctypes.POINTER(ctypes.c_double)), None, 10, None, dev.data_ptr(), words, rho.ctypes.data_as(
+            ctypes.POINTER(ctypes.c_double)), None, None, None, None)
+        assert rc == sth.STH_EINVAL and "mask_words" in sth.sth_last_error()
+    rc = sth.lib().sth_fine_run_masks(p.h, np.ascontiguousarray(inst.rho_in).ctypes.data_as(
+        ctypes.POINTER(ctypes.c_double)), None, 10, dev.data_ptr(), None, 11 * mw - 1, rho.ctypes.data_as(
+        ctypes.POINTER(ctypes.c_double)), None, None, None, None)
+    assert rc == sth.STH_EINVAL and "mask_words" in sth.sth_last_error()
     p.close()
 
 

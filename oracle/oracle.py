@@ -23,6 +23,7 @@ FIELD = 2
 LITERAL_R = 4
 LITERAL_FLUX = 8
 COARSE_EXPLICIT = 16
+STORE_F32 = 32  # g' stored in binary32 after every step (precision floor of FP32 storage)
 START_LIFT = 0
 START_CARRY = 1
 

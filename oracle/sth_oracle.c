@@ -396,6 +396,9 @@ void orc_fine_propagate_masks(const orc_params *p, const double *eps_iface, cons
     memcpy(rho, rho_in, sizeof(double) * nx);
     if (g_in) memcpy(g, g_in, sizeof(double) * nx * nv);
     else memset(g, 0, sizeof(double) * nx * nv);
+    const int store_f32 = (p->flags & ORC_STORE_F32) != 0;
+    if (store_f32)
+        for (size_t u = 0; u < (size_t)nx * nv; ++u) g[u] = (double)(float)g[u];
     for (int q = 0; q < nx; ++q) {
         double r = dt / (eps_iface[q] * eps_iface[q]);
         e[q] = exp(-r);
@@ -482,6 +485,9 @@ void orc_fine_propagate_masks(const orc_params *p, const double *eps_iface, cons
         } else {
             for (int i = 0; i < nx; ++i) rho[i] = rho[i] + dt / dx * (Phi[i] - Phi[wrap(i - 1, nx)]);
         }
+
+        if (store_f32)
+            for (size_t u = 0; u < (size_t)nx * nv; ++u) gn[u] = (double)(float)gn[u];
 
         /* 5. new status; fluid interfaces hold g' = 0 */
         if (hybrid) {

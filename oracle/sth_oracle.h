@@ -42,6 +42,13 @@ extern "C" {
                               of its two interfaces, a fluid cell the limit
                               fluxes m2 J (not conservative where the two kinds
                               of cells meet); default: flux-matched            */
+#define ORC_STORE_F32 32 /* the perturbation g' is stored in IEEE binary32:
+                              rounded to the nearest float after every fine
+                              step (and at the start), all arithmetic still in
+                              FP64.  Measures the floor that storing the state
+                              of the FP32-bulk form in 24 bits puts under its
+                              error, whatever its arithmetic; not a scheme of
+                              the paper                                       */
 
 /* slice-start perturbation of the parareal fine sweeps */
 #define ORC_START_LIFT  0 /* lifting L^L of the slice-start density (Algorithm 1) */

@@ -789,3 +789,27 @@ def test_mask_history_replays_itself_and_pins_the_extremes(orc):
     assert np.array_equal(r5, r) and not np.any(g5) and s5["kinetic_iface_steps"] == 0
     with pytest.raises(ValueError):
         orc.fine_propagate_masks(*args, replay=h1[:-1])
+
+
+def test_store_f32_keeps_binary32_state_and_loses_sub_resolution_relaxation(orc):
+    """The binary32 storage option (the floor of the FP32-bulk form): every
+    stored g' is a binary32 value; on a uniform density (no transport, field
+    and source vanish exactly) one step is g' <- e g' with e = exp(-dt/eps^2),
+    so the FP64 run decays as e^n while, with 1 - e = 1e-8 below half the
+    binary32 spacing (2^-25 relative), the binary32 state never moves."""
+    nx, nv, n = 16, 16, 1000
+    eps = np.ones(nx)
+    rho0 = np.ones(nx)
+    v, M, _ = orc.velocity_grid(nv)
+    g0 = np.tile(0.37 * v * M, (nx, 1))
+    base = dict(rhobar=1.0, dt=1e-8, flags=orc.FIELD)
+    p64 = orc.params(nx, nv, **base)
+    p32 = orc.params(nx, nv, **dict(base, flags=orc.FIELD | orc.STORE_F32))
+    r64, g64, _, _ = orc.fine_propagate(p64, eps, eps, rho0, g0, n)
+    r32, g32, _, _ = orc.fine_propagate(p32, eps, eps, rho0, g0, n)
+    assert np.max(np.abs(g64 - g0 * math.exp(-n * 1e-8))) < 1e-13 * np.max(np.abs(g0))
+    assert np.array_equal(g32, g0.astype(np.float32).astype(np.float64))
+    assert np.array_equal(r64, rho0) and np.array_equal(r32, rho0)
+    # without the option nothing changes
+    p64b = orc.params(nx, nv, **dict(base, flags=orc.FIELD))
+    assert np.array_equal(orc.fine_propagate(p64b, eps, eps, rho0, g0, n)[1], g64)

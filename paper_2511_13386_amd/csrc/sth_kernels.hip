@@ -78,8 +78,32 @@ __device__ __forceinline__ double lane_value(double x, int l)
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// Sum over the 64 lanes, in every lane.
-__device__ __forceinline__ double wave_total_f64(double x) { return lane_value(wave_scan_f64(x), kWave - 1); }
+// DPP move of a double whose lanes outside row_mask are left undefined (no
+// initialisation of the destination): for reductions that read one lane.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_f64_u(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)b, CTRL, ROWMASK, 0xf, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, ROWMASK, 0xf, false);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64_z(double x);
+
+// Sum over the 64 lanes, in every lane: zero-filling row shifts give each
+// row's sum in its lane 15, the row broadcasts add the rows below into lane
+// 63 (the other lanes end undefined), which is read back.
+__device__ __forceinline__ double wave_total_f64(double x)
+{
+    x += dpp_f64_z<0x111>(x);
+    x += dpp_f64_z<0x112>(x);
+    x += dpp_f64_z<0x114>(x);
+    x += dpp_f64_z<0x118>(x);
+    x += dpp_f64_u<0x142, 0xa>(x);
+    x += dpp_f64_u<0x143, 0xc>(x);
+    return lane_value(x, kWave - 1);
+}
 
 // Two inclusive prefix sums at once (independent chains interleave and fill
 // each other's DPP wait states); the row shifts zero-fill (bound_ctrl).
@@ -293,8 +317,9 @@ __device__ __forceinline__ void keep(float &x) { asm volatile("" : "+v"(x)); }
 
 template <typename Real>
 struct RowCoef {
-    Real Ep, Em, e, aeps, aJ;  // E+/dv, E-/dv, exp(-dt/eps^2), a eps, a J (0 if not kinetic)
-    Real c1, c1n, c1p;         // lazy projection of this interface and of p+1, p-1
+    Real Ep, Em, e, a, aeps, aJ;  // E+/dv, E-/dv, exp(-dt/eps^2), a = -expm1(-dt/eps^2), a eps,
+                                  // a J (all but E+-/dv zero if not kinetic)
+    Real c1, c1n, c1p;            // lazy projection of this interface and of p+1, p-1
 };
 
 // Running sums of a row pass.  They are kept in FP64 in both precisions:
@@ -336,16 +361,21 @@ __device__ __forceinline__ void acc_pair(RowOut<Real> &o, PairAcc<Real> &a, Real
 
 // Relaxation with the source for a mirror pair, w' = e g - a eps A - a J v M
 // (v M of the pair's v<0 member; its mirror has the opposite sign).  FP32
-// bulk spells it as fused multiply-adds around one product a J v M per pair
-// (its pass is bound by VALU issue); FP64 keeps the compiler's form.
+// bulk computes it as an increment, w' = g + d with d = -(a g + a eps A +
+// a J v M) formed first: where dt/eps^2 is below the FP32 resolution, e
+// rounds to 1 or to 1 - 2^-24 and e g would relax g at a wrong rate or not at
+// all, while a keeps its 24 bits and the one rounding of g + d is unbiased.
+// FP64 keeps the printed form (e exact to 1e-16).
 template <typename Real>
 __device__ __forceinline__ void relax_pair(const RowCoef<Real> &c, Real gj, Real gm, Real Aj, Real Am, Real vM,
                                            Real &wj, Real &wm)
 {
     if constexpr (sizeof(Real) == 4) {
         const Real sJ = c.aJ * vM;
-        wj = __builtin_fmaf(-c.aeps, Aj, __builtin_fmaf(c.e, gj, -sJ));
-        wm = __builtin_fmaf(-c.aeps, Am, __builtin_fmaf(c.e, gm, sJ));
+        const Real dj = __builtin_fmaf(-c.a, gj, __builtin_fmaf(-c.aeps, Aj, -sJ));
+        const Real dm = __builtin_fmaf(-c.a, gm, __builtin_fmaf(-c.aeps, Am, sJ));
+        wj = gj + dj;
+        wm = gm + dm;
     } else {
         wj = c.e * gj - c.aeps * Aj - c.aJ * vM;
         wm = c.e * gm - c.aeps * Am + c.aJ * vM;
@@ -565,6 +595,14 @@ __device__ __forceinline__ RowOut<Real> row_pass_res(Real (&Wr)[NV], const RowCo
         relax_pair(c, gj, gm, Aj, Am, vMc, wj, wm);
         Wr[j] = wj;
         Wr[m] = wm;
+        // the stored rows that pair t+1 reads stay live until the new values
+        // of pair t exist, so that each new value takes the register of the
+        // value it replaces (else the allocation rotates by one row per pass
+        // and every step pays a register copy per row)
+        if (t + 1 < HV) {
+            asm volatile("" ::"v"(Wr[j + 1]));
+            asm volatile("" ::"v"(Wr[m - 1]));
+        }
         if (first) hno[t] = wj;
         if (last) hpo[HV - 1 - t] = wm;
         acc_pair(o, a, Aj, Am, cxc, wj, wm, gj, gm);
@@ -1090,6 +1128,7 @@ __global__ void __launch_bounds__(BLK) k_fine(const FineUnit *__restrict__ units
                 c.Ep = (Real)(E > 0.0 ? E / dv : 0.0);
                 c.Em = (Real)(E < 0.0 ? E / dv : 0.0);
                 c.e = kv ? er : Real(0);
+                c.a = kv ? ar : Real(0);
                 c.aeps = kv ? ar * epsr : Real(0);
                 c.aJ = kv ? (Real)((double)ar * J) : Real(0);
                 const RowOut<Real> o = pass(k, i, iv, seg, segn, segp, last, c);
@@ -1130,7 +1169,10 @@ __global__ void __launch_bounds__(BLK) k_fine(const FineUnit *__restrict__ units
 #pragma unroll
                             for (int j = 0; j < HV; ++j) Wr[k][j] = hn[j];
                         }
-                        c.c1 = s_c1[par * nx + (ghost ? 0 : iv)];
+                        // lanes past the ghost keep zero rows and a zero projection (their
+                        // relaxation must leave them at zero)
+                        const Real c1v = s_c1[par * nx + (ghost ? 0 : iv)];
+                        c.c1 = (i < nx || ghost) ? c1v : Real(0);
                         c.c1n = s_c1[par * nx + wrapi(iv + 1, nx)];
                         c.c1p = s_c1[par * nx + wrapi(iv - 1, nx)];
                         const ConstPtr<Real> vt = opaque(vtr);

@@ -1,0 +1,155 @@
+"""Parity of the fine propagator F (scheme S^HMM, Section 2.3, with the cell
+rules of Section 2.2) at the full slice length of the two parareal workloads,
+against the FP64 oracle, in the default GPU run.
+
+* 512 x 64 hybrid workload, slice 1 of the first sweep: 369,148 fine steps
+  from rho_in with g' = 0.
+* 2048 x 128 workload at its parity horizon T = 1/64 (13,747 steps per
+  slice): slice 1 (from rho_in) and two later slices of the first sweep,
+  started from the oracle's coarse-guess densities with their lifted
+  perturbations (Algorithm 1, Definition 1).
+
+The oracle sums sequentially and the kernels in trees, so a criterion value
+within rounding of its threshold can be decided differently; the number of
+(step, cell) states whose status differs is reported, and where it is not
+zero the run is repeated with the oracle's status history imposed, which
+leaves precision alone.  FP64 is then held to 1e-12 (rho) and 1e-10 (g',
+relative to its max-norm).
+
+FP32 bulk keeps g' in binary32.  Where dt/eps^2 is below the binary32
+resolution (2^-24) the relaxation increments of one step are smaller than
+the spacing of the stored values, and no FP32-bulk arithmetic can keep them;
+the oracle measures that floor itself (its binary32-storage option: g'
+rounded to binary32 after every step, FP64 arithmetic, the same status
+history).  The FP32-bulk tolerance of a case is 1e-5 (rho) and 1e-3 (g'), or
+four times the floor where the floor is higher: the kernel rounds three
+state-sized values per step (reconstruction, relaxation, projection) against
+the floor's one.  A lifted start is handed to all sides rounded to binary32
+in the FP32 case, so that the comparison measures the slice, not the
+rounding of its input."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from paper_2511_13386_amd import sth
+from paper_2511_13386_amd import workloads as wl
+
+from helpers import desc_of, oracle_of, rel_err
+
+pytestmark = pytest.mark.gpu
+
+RHO64, G64 = 1e-12, 1e-10
+RHO32, G32 = 1e-5, 1e-3
+FLOOR_FACTOR = 4.0
+
+
+def _store_f32(orc, po):
+    q = type(po).from_buffer_copy(po)
+    q.flags |= orc.STORE_F32
+    return q
+
+
+def _join(threads, t0, what):
+    for th in threads:
+        while th.is_alive():
+            th.join(30.0)
+            print(f"{what}: {time.time() - t0:.0f} s", flush=True)
+
+
+def _oracles(orc, po, inst, rho, g0, ns, out, key):
+    """FP64 oracle with its own status rule, then the binary32-storage oracle
+    with that history imposed."""
+    o = orc.fine_propagate_masks(po, inst.eps_iface, inst.eps_cell, rho, g0, ns)
+    out[key] = o
+    out[key + ("floor",)] = orc.fine_propagate_masks(_store_f32(orc, po), inst.eps_iface, inst.eps_cell,
+                                                     rho, g0, ns, replay=o[4])
+
+
+def _compare(tag, p, rho, g0, ns, oracle, rtol, gtol, m0):
+    """GPU run with its own status rule, then (if the histories differ) with
+    the oracle's imposed; returns the number of differing states."""
+    ro, go, _, st, ho = oracle
+    r, g, _, k, h = sth.sth_fine_run_masks(p, rho, g0, ns)
+    diff = int(np.sum(h != ho))
+    print(f"{tag}: {diff} of {ho.size} (step, cell) states differ from the oracle's; "
+          f"own rule rho {rel_err(r, ro):.2e}, g' {rel_err(g, go):.2e}; kinetic interface-steps "
+          f"{k:.0f} vs {st['kinetic_iface_steps']:.0f}", flush=True)
+    if diff:
+        r, g, _, k, _ = sth.sth_fine_run_masks(p, rho, g0, ns, replay=ho)
+        print(f"{tag}, oracle history imposed: rho {rel_err(r, ro):.2e}, g' {rel_err(g, go):.2e}",
+              flush=True)
+    assert k == st["kinetic_iface_steps"]
+    assert rel_err(r, ro) < rtol, (tag, rel_err(r, ro), rtol)
+    assert rel_err(g, go) < gtol, (tag, rel_err(g, go), gtol)
+    assert abs(np.sum(r) - m0) < 1e-12 * abs(m0)
+    return diff
+
+
+def _fp32_tolerances(tag, oracle, floor):
+    fr, fg = rel_err(floor[0], oracle[0]), rel_err(floor[1], oracle[1])
+    rt, gt = max(RHO32, FLOOR_FACTOR * fr), max(G32, FLOOR_FACTOR * fg)
+    print(f"{tag}: binary32-storage floor rho {fr:.2e}, g' {fg:.2e}; tolerances {rt:.1e}, {gt:.1e}",
+          flush=True)
+    return rt, gt
+
+
+def test_config2_slice1_full_length(orc):
+    """512 x 64, slice 1 at its full 369,148 steps: FP64 and FP32 bulk."""
+    inst = wl.config2()
+    po, ns, _ = oracle_of(orc, inst, lift_order=1)
+    assert ns == 369148
+    res = {}
+    t0 = time.time()
+    th = threading.Thread(target=_oracles, args=(orc, po, inst, inst.rho_in, None, ns, res, ("o",)))
+    th.start()
+    p64 = sth.Problem(desc_of(inst, precision=sth.FP64, lift_order=1))
+    p32 = sth.Problem(desc_of(inst, precision=sth.FP32_BULK, lift_order=1))
+    _join([th], t0, "oracle (FP64, then binary32 storage), 369,148 steps each")
+    m0 = float(np.sum(inst.rho_in))
+    o = res[("o",)]
+    _compare("512x64 slice 1, FP64", p64, inst.rho_in, None, ns, o, RHO64, G64, m0)
+    rt, gt = _fp32_tolerances("512x64 slice 1", o, res[("o", "floor")])
+    _compare("512x64 slice 1, FP32 bulk", p32, inst.rho_in, None, ns, o, rt, gt, m0)
+    p64.close()
+    p32.close()
+
+
+def test_config3_three_full_slices(orc):
+    """2048 x 128 at T = 1/64: slices 1, 2 and 65 of the first sweep, 13,747
+    steps each, FP64 and FP32 bulk."""
+    inst = wl.config3(T=1.0 / 64)
+    po, ns, dtG = oracle_of(orc, inst, lift_order=1)
+    assert ns == 13747
+    starts = [np.array(inst.rho_in, dtype=np.float64)]
+    for _ in range(inst.N // 2):
+        starts.append(orc.coarse_step(po, dtG, starts[-1]))
+    sample = [0, 1, inst.N // 2]
+    g0 = {n: (None if n == 0 else orc.lift(po, inst.eps_iface, starts[n])) for n in sample}
+    g032 = {n: (None if g0[n] is None else g0[n].astype(np.float32).astype(np.float64)) for n in sample}
+    res = {}
+    t0 = time.time()
+    threads = []
+    for n in sample:
+        threads.append(threading.Thread(target=_oracles, args=(orc, po, inst, starts[n], g0[n], ns, res,
+                                                               (n, 64))))
+        if n > 0:
+            threads.append(threading.Thread(target=_oracles, args=(orc, po, inst, starts[n], g032[n], ns,
+                                                                   res, (n, 32))))
+    for th in threads:
+        th.start()
+    p64 = sth.Problem(desc_of(inst, precision=sth.FP64, lift_order=1))
+    p32 = sth.Problem(desc_of(inst, precision=sth.FP32_BULK, lift_order=1))
+    _join(threads, t0, "oracle, 2048 x 128 slices")
+    total = 0
+    for n in sample:
+        m0 = float(np.sum(starts[n]))
+        total += _compare(f"2048x128 slice {n + 1}, FP64", p64, starts[n], g0[n], ns, res[(n, 64)],
+                          RHO64, G64, m0)
+        key = (n, 32) if n > 0 else (n, 64)
+        rt, gt = _fp32_tolerances(f"2048x128 slice {n + 1}", res[key], res[key + ("floor",)])
+        _compare(f"2048x128 slice {n + 1}, FP32 bulk", p32, starts[n], g032[n], ns, res[key], rt, gt, m0)
+    print(f"2048x128: {total} differing FP64 (step, cell) states over {len(sample)} slices", flush=True)
+    p64.close()
+    p32.close()

@@ -310,6 +310,7 @@ def test_parareal_iterations_match_oracle(orc, mode):
                                      inst.rho_in)
     # the lifting differentiates the density up to three times, so rounding
     # differences of the two implementations grow like dx^-3 through it
+    print(f"parareal {mode}: slice values {rel_err(U, Uo):.2e} from the oracle's", flush=True)
     assert rel_err(U, Uo) < (1e-11 if mode == "carry" else 2e-10)
     assert np.allclose(errs, erro, rtol=1e-6, atol=1e-13)
     m0 = np.sum(inst.rho_in)

@@ -27,12 +27,11 @@ pytestmark = [pytest.mark.gpu,
                                  reason="minutes of oracle time; set STH_LONG_PARITY=1")]
 
 RHO64, G64 = 1e-12, 1e-10
-# FP32 bulk over 13,747 steps of a 2048-cell slice: the FP32 rounding of g'
-# accumulates beyond the short-run tolerances (2e-6, 2e-4), and a lifted
-# start rounded to FP32 moves the slice end further (the slice map amplifies
-# high-frequency start differences about a thousandfold); the config-3
-# tolerances of the FP32-bulk form hold: rho 1e-4, g' 2e-3 relative
-RHO32, G32 = 1e-4, 2e-3
+# FP32 bulk against the oracle run from the same start rounded to FP32 (the
+# slice map amplifies high-frequency start differences about a thousandfold,
+# so the rounding of a lifted start is an input difference, not the FP32
+# arithmetic of the slice)
+RHO32, G32 = 1e-5, 1e-3
 
 
 def _wait(threads, t0, what):
@@ -45,8 +44,14 @@ def _wait(threads, t0, what):
 def test_config3_one_iteration_reported(orc):
     """One parareal iteration of the whole problem: mass exact in both
     precisions, the kinetic work within 1e-6 (FP64) and 1e-5 (FP32 bulk) and
-    the successive error within 1e-5 and 1e-4 of the oracle's, the slice values
-    reported (decisions taken differently move them discretely)."""
+    the successive error within 1e-5 and 1e-4 of the oracle's.  The slice
+    values are reported as a number, not asserted: from slice 2 on the starts
+    are liftings of coarse values that differ from the oracle's by rounding,
+    and the lifting (a third derivative at dx = 1/2048) and the slice map
+    amplify that; slice parity from identical starts, with the oracle's
+    status history imposed where decisions differ, is asserted in
+    test_config3_slices_with_status_histories and, for three slices in the
+    default run, in test_config_parity.py."""
     inst = wl.config3(T=1.0 / 64)
     K = 1
     po, ns, dtG = oracle_of(orc, inst, lift_order=1)
@@ -77,7 +82,7 @@ def test_config3_one_iteration_reported(orc):
           f"{np.max(per[:first]) if first else 0.0:.1e}", flush=True)
     assert abs(k64 - kin) < 1e-6 * kin and abs(k32 - kin) < 1e-5 * kin
     assert abs(e64[0] - erro[0]) < 1e-5 * erro[0] and abs(e32[0] - erro[0]) < 1e-4 * erro[0]
-    assert rel_err(U64, Uo) < 1e-2 and rel_err(U32, Uo) < 1e-2
+    assert abs(np.max(np.abs(U64[1] - Uo[1]))) < RHO64 * np.max(np.abs(Uo[1]))
     for U in (U64, U32):
         assert np.max(np.abs(U.sum(axis=1) - m0)) < 1e-12 * m0
 
@@ -98,6 +103,10 @@ def test_config3_slices_with_status_histories(orc):
     def run(n):
         g0 = None if n == 0 else orc.lift(po, inst.eps_iface, starts[n])
         res[n] = (g0,) + tuple(orc.fine_propagate_masks(po, inst.eps_iface, inst.eps_cell, starts[n], g0, ns))
+        if g0 is not None:
+            g032 = g0.astype(np.float32).astype(np.float64)
+            res[(n, 32)] = (g032,) + tuple(orc.fine_propagate_masks(po, inst.eps_iface, inst.eps_cell,
+                                                                    starts[n], g032, ns))
 
     t0 = time.time()
     threads = [threading.Thread(target=run, args=(n,)) for n in sample]
@@ -117,16 +126,20 @@ def test_config3_slices_with_status_histories(orc):
         r64, g64, _, k64, h64 = sth.sth_fine_run_masks(p64, starts[n], g0, ns)
         diff = int(np.sum(h64 != ho))
         total += diff
-        r32, g32, _, _, h32 = sth.sth_fine_run_masks(p32, starts[n], g0, ns)
-        print(f"slice {n + 1}: FP64 {diff} and FP32 bulk {int(np.sum(h32 != ho))} of {ho.size} (step, cell) "
-              f"states differ from the oracle's; rho {rel_err(r64, ro):.1e} / {rel_err(r32, ro):.1e}", flush=True)
+        g32s, ro32, go32, _, _, ho32 = res[(n, 32)] if n > 0 else res[n]
+        r32, g32, _, _, h32 = sth.sth_fine_run_masks(p32, starts[n], g32s, ns)
+        print(f"slice {n + 1}: FP64 {diff} and FP32 bulk {int(np.sum(h32 != ho32))} of {ho.size} (step, cell) "
+              f"states differ from the oracle's; rho {rel_err(r64, ro):.1e} / {rel_err(r32, ro32):.1e}",
+              flush=True)
         if diff == 0:
             assert k64 == st["kinetic_iface_steps"]
         else:
             r64, g64, _, k64, _ = sth.sth_fine_run_masks(p64, starts[n], g0, ns, replay=ho)
         assert rel_err(r64, ro) < RHO64 and rel_err(g64, go) < G64
-        r32, g32, _, _, _ = sth.sth_fine_run_masks(p32, starts[n], g0, ns, replay=ho)
-        assert rel_err(r32, ro) < RHO32 and rel_err(g32, go) < G32
+        r32, g32, _, _, _ = sth.sth_fine_run_masks(p32, starts[n], g32s, ns, replay=ho32)
+        print(f"slice {n + 1}, FP32 bulk with the oracle's history: rho {rel_err(r32, ro32):.1e}, "
+              f"g' {rel_err(g32, go32):.1e}", flush=True)
+        assert rel_err(r32, ro32) < RHO32 and rel_err(g32, go32) < G32
     p64.close()
     p32.close()
     print(f"FP64: {total} differing (step, cell) states over {len(sample)} slices", flush=True)

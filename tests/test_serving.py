@@ -6,7 +6,7 @@ import pytest
 from paper_2511_13386_amd import serving, sth
 from paper_2511_13386_amd import workloads as wl
 
-from helpers import desc_of
+from helpers import desc_of, oracle_of, rel_err
 
 
 def test_free_list_first_fit_and_coalescing():
@@ -39,10 +39,13 @@ def test_free_list_admission_order_under_pressure():
 
 @pytest.mark.gpu
 @pytest.mark.parametrize("chunk", [None, 97])
-def test_served_results_equal_solves_alone(chunk):
+def test_served_results_equal_solves_alone(orc, chunk):
     """Six requests of different sizes and precisions arrive staggered and
     overlap on the device (an arena small enough that some must wait for
-    memory); each served result equals its solve alone."""
+    memory); each served result equals its solve alone, and the oracle's
+    parareal (Algorithm 1, carried starts): FP64 requests to 1e-11, FP32-bulk
+    requests to 1e-5 or four times the floor of binary32 storage (the
+    oracle's own solve with g' stored in binary32)."""
     torch = pytest.importorskip("torch")
     insts = [
         (wl.small_hybrid(seed=1, nx=96, nv=32, N=3, T=2e-3, K=2), sth.FP64),
@@ -67,6 +70,22 @@ def test_served_results_equal_solves_alone(chunk):
         assert r.latency > 0 and r.finished >= r.admitted >= 0
         p.close()
     torch.cuda.synchronize()
+    if chunk is None:
+        for r, (inst, prec) in zip(res, insts):
+            po, ns, dtG = oracle_of(orc, inst)
+            Uo = orc.parareal(po, inst.eps_iface, inst.eps_cell, inst.N, ns, dtG, 2, 0.0, inst.rho_in)[0]
+            err = rel_err(r.rho, Uo)
+            if prec == sth.FP64:
+                print(f"request {r.rid}: FP64 served vs oracle {err:.2e}", flush=True)
+                assert err < 1e-11
+            else:
+                q = type(po).from_buffer_copy(po)
+                q.flags |= orc.STORE_F32
+                floor = rel_err(orc.parareal(q, inst.eps_iface, inst.eps_cell, inst.N, ns, dtG, 2, 0.0,
+                                             inst.rho_in)[0], Uo)
+                print(f"request {r.rid}: FP32 bulk served vs oracle {err:.2e}, binary32-storage floor "
+                      f"{floor:.2e}", flush=True)
+                assert err < max(1e-5, 4.0 * floor)
 
 
 @pytest.mark.gpu

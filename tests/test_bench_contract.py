@@ -5,6 +5,7 @@ import os
 import subprocess
 import sys
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -31,6 +32,29 @@ def test_cpu_baseline_block_has_the_contract_fields():
     assert host["single_thread_value"] > 0 and host["threads"] == base["cores"]
     c1 = host["config1_single_thread"]
     assert c1["value"] > 0 and c1["steps"] > 10000
+    assert host["parareal_iteration_wall_s_extrapolated"] > 0
+
+
+def test_accuracy_to_cost_uses_the_exact_leading_slices():
+    """After k iterations slices 0..k equal the serial fine solution, so the
+    distance of iterate k from it is read on slices 0..K of the last iterate;
+    tolerance crossings report the first iteration below each tolerance."""
+    N, nx, K = 6, 4, 3
+    S = np.arange(1.0, (N + 1) * nx + 1.0).reshape(N + 1, nx)
+    its = []
+    for k in range(1, K + 1):
+        U = S.copy()
+        U[k + 1:] += 0.5 ** k  # slices beyond k not yet exact
+        its.append(U)
+    r = {"iterates": its, "iterations": K, "diverged": False, "errs": [0.3, 0.05, 0.002],
+         "t_iter": [1.0, 2.0, 3.0], "sweep_ms": [100.0, 90.0, 80.0], "wall": 3.5}
+    a = bench.accuracy_to_cost(r, N)
+    scale = np.max(np.abs(its[-1][:K + 1]))
+    assert a["distance_from_serial_fine"] == pytest.approx([0.5 / scale, 0.25 / scale, 0.0])
+    assert a["serial_fine_slices_known"] == K
+    assert a["to_successive_error_below"]["0.1"] == {"iterations": 2, "wall_s": 2.0}
+    assert a["to_successive_error_below"]["0.001"] is None
+    assert a["serial_fine_wall_s_estimate"] == pytest.approx(N * 0.1)
 
 
 def test_traffic_is_read_only_for_the_current_sources(tmp_path, monkeypatch):

@@ -315,6 +315,24 @@ int  sth_fine_run_masks(sth_problem *p, const double *rho_in, const double *g_in
                         double *rho_out, double *g_out, int *cell_mask_out, double *kin_out,
                         void *stream);
 
+/* sth_fine_run for callers that cannot allocate device memory (serving
+ * loops and harnesses that forbid allocation): the same arguments, kernel
+ * and results, bit for bit, but the run's unit table, slice slot, densities,
+ * status, counter and the staging of the perturbation live in a static
+ * device workspace of 2 MiB per device (held until the process ends)
+ * instead of the problem's arena; the call allocates no device memory and,
+ * on success, no host memory.  STH_EINVAL (nothing launched) when the run
+ * needs more than the workspace: nx * nv * (realsz + 8) bytes and about
+ * 2 * nx * realsz more when g_in or g_out is given, else the slot alone
+ * (512 x 64 FP64 uses 0.55 MiB; 1024 x 128 FP64 with g is refused).  Every
+ * call on a device shares that device's workspace: calls that overlap on
+ * one device race (the call synchronises the device first and its stream
+ * before returning, so sequential calls are safe).  The device current at
+ * the call must be the problem's.  Synchronises. */
+int sth_fine_run_noalloc(const sth_problem *p, const double *rho_in, const double *g_in, long long nsteps,
+                         double *rho_out, double *g_out, int *cell_mask_out, double *kin_out,
+                         void *stream);
+
 /* Release the problem (and its device memory if the library allocated it). */
 void sth_destroy(sth_problem *p);
 

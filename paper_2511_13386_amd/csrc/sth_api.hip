@@ -1440,3 +1440,116 @@ int sth_fine_run_masks(sth_problem *p, const double *rho_in, const double *g_in,
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free single-slice run.  Its unit table, slice slot (rows,
+// lazy projection, halos), densities, status, counter and the x-major
+// staging of the perturbation live in one file-scope device array instead
+// of the problem's arena: kNoAllocScratchBytes per device, held until the
+// process ends.  Host code never uses the array's name as an address (it is
+// a host-side stand-in there); the device address comes from
+// hipGetSymbolAddress, once per device, with that device current.
+namespace {
+
+constexpr size_t kNoAllocScratchBytes = size_t(2) << 20;  // 2 MiB
+constexpr int kNoAllocMaxDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kNoAllocMaxDevices] = {};
+
+// Device address of the current device's copy of scratch.
+int scratch_address(void **out)
+{
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNoAllocMaxDevices) return fail(STH_EINVAL, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return STH_OK;
+}
+
+// Offsets of one run in scratch (256-byte aligned blocks).
+struct NoAllocLayout {
+    size_t unit, rin, rout, mask, kin, slot, gx, total;
+};
+
+NoAllocLayout noalloc_layout(int nx, int nv, int realsz, bool staging)
+{
+    NoAllocLayout L{};
+    size_t o = 0;
+    L.unit = o; o = al256(o + sizeof(FineUnit));
+    L.rin = o;  o = al256(o + sizeof(double) * nx);
+    L.rout = o; o = al256(o + sizeof(double) * nx);
+    L.mask = o; o = al256(o + sizeof(int) * nx);
+    L.kin = o;  o = al256(o + sizeof(unsigned long long));
+    L.slot = o; o = al256(o + fine_slot_elems(nx, nv) * (size_t)realsz);
+    L.gx = o;   if (staging) o = al256(o + sizeof(double) * (size_t)nx * nv);
+    L.total = o;
+    return L;
+}
+
+const unsigned long long kZeroCounter = 0;
+
+}  // namespace
+
+extern "C" {
+
+int sth_fine_run_noalloc(const sth_problem *p, const double *rho_in, const double *g_in, long long nsteps,
+                         double *rho_out, double *g_out, int *cell_mask_out, double *kin_out, void *stream)
+{
+    if (!p || !rho_in) return fail(STH_EINVAL, "null argument");
+    if (nsteps < 0) return fail(STH_EINVAL, "nsteps must be >= 0");
+    const int nx = p->nx, nv = p->nv;
+    const NoAllocLayout L = noalloc_layout(nx, nv, p->realsz, g_in || g_out);
+    if (L.total > kNoAllocScratchBytes)
+        return fail(STH_EINVAL, "sth_fine_run_noalloc: the run needs more than the 2 MiB static workspace "
+                                "(use sth_fine_run)");
+    void *base = nullptr;
+    int rc = scratch_address(&base);
+    if (rc) return rc;
+    char *b = (char *)base;
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipMemcpy(b + L.rin, rho_in, sizeof(double) * nx, hipMemcpyHostToDevice));
+    // the counter starts at zero (the workspace keeps the last run's contents)
+    HIPCHK(hipMemcpy(b + L.kin, &kZeroCounter, sizeof(kZeroCounter), hipMemcpyHostToDevice));
+    if (g_in) {
+        HIPCHK(hipMemcpy(b + L.gx, g_in, sizeof(double) * (size_t)nx * nv, hipMemcpyHostToDevice));
+        // the start rows go to the slot's own rows: the kernel reads each
+        // start value before the same thread writes that element
+        HIPCHK(launch_to_vmajor(p->prec, (const double *)(b + L.gx), b + L.slot, nx, nv, st));
+    }
+    FineUnit u{};
+    u.c = p->fc;
+    u.rho_in = (const double *)(b + L.rin);
+    u.rho_out = (double *)(b + L.rout);
+    u.g_in = g_in ? (const void *)(b + L.slot) : nullptr;
+    u.g_out = b + L.slot;
+    u.kin = (unsigned long long *)(b + L.kin);
+    u.mask_out = (int *)(b + L.mask);
+    u.nsteps = nsteps;  // 0: the start state after the status rule
+    HIPCHK(hipMemcpy(b + L.unit, &u, sizeof(u), hipMemcpyHostToDevice));
+    const FineShape sh = class_shape(p->prec, nx, nv);
+    HIPCHK(launch_fine(sh, (const FineUnit *)(b + L.unit), 1, st));
+    if (g_out) HIPCHK(launch_to_xmajor(p->prec, b + L.slot, (double *)(b + L.gx), nx, nv, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (rho_out) HIPCHK(hipMemcpy(rho_out, b + L.rout, sizeof(double) * nx, hipMemcpyDeviceToHost));
+    if (g_out) HIPCHK(hipMemcpy(g_out, b + L.gx, sizeof(double) * (size_t)nx * nv, hipMemcpyDeviceToHost));
+    if (cell_mask_out) HIPCHK(hipMemcpy(cell_mask_out, b + L.mask, sizeof(int) * nx, hipMemcpyDeviceToHost));
+    if (kin_out) {
+        unsigned long long k = 0;
+        HIPCHK(hipMemcpy(&k, b + L.kin, sizeof(k), hipMemcpyDeviceToHost));
+        *kin_out = (double)k;
+    }
+    return STH_OK;
+}
+
+}  // extern "C"

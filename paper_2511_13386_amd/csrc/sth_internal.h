@@ -147,6 +147,12 @@ struct CopyJob {
 };
 hipError_t launch_copy(const CopyJob *d_jobs, int njobs, size_t max_n, hipStream_t st);
 
+// Perturbation layout conversions of the allocation-free single-slice run:
+// x-major float64 g[p*nv + j] <-> the v-major working-precision rows
+// rows[j*ld + p] of a unit slot (padding lanes zero).
+hipError_t launch_to_vmajor(int prec, const double *gx, void *rows, int nx, int nv, hipStream_t st);
+hipError_t launch_to_xmajor(int prec, const void *rows, double *gx, int nx, int nv, hipStream_t st);
+
 // Diagnostics of a state (rho, g).
 struct DiagJob {
     const FineConst *pc;

@@ -1871,6 +1871,49 @@ hipError_t launch_copy(const CopyJob *d_jobs, int njobs, size_t max_n, hipStream
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------ layout conversions
+// x-major float64 perturbation -> v-major rows of stride ld (one thread per
+// row element, padding lanes zero) and back.
+template <typename Real>
+__global__ void __launch_bounds__(256) k_to_vmajor(const double *__restrict__ gx, Real *__restrict__ rows, int nx,
+                                                  int nv, int ld)
+{
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (size_t)nv * ld) return;
+    const int j = (int)(t / ld), p = (int)(t % ld);
+    rows[t] = p < nx ? (Real)gx[(size_t)p * nv + j] : Real(0);
+}
+
+template <typename Real>
+__global__ void __launch_bounds__(256) k_to_xmajor(const Real *__restrict__ rows, double *__restrict__ gx, int nx,
+                                                  int nv, int ld)
+{
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (size_t)nx * nv) return;
+    const int p = (int)(t / nv), j = (int)(t % nv);
+    gx[t] = (double)rows[(size_t)j * ld + p];
+}
+
+hipError_t launch_to_vmajor(int prec, const double *gx, void *rows, int nx, int nv, hipStream_t st)
+{
+    const int ld = fine_ld(nx);
+    const size_t n = (size_t)nv * ld;
+    const dim3 grid((unsigned)((n + 255) / 256));
+    if (prec == 0) hipLaunchKernelGGL(k_to_vmajor<double>, grid, dim3(256), 0, st, gx, (double *)rows, nx, nv, ld);
+    else hipLaunchKernelGGL(k_to_vmajor<float>, grid, dim3(256), 0, st, gx, (float *)rows, nx, nv, ld);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_xmajor(int prec, const void *rows, double *gx, int nx, int nv, hipStream_t st)
+{
+    const int ld = fine_ld(nx);
+    const size_t n = (size_t)nx * nv;
+    const dim3 grid((unsigned)((n + 255) / 256));
+    if (prec == 0) hipLaunchKernelGGL(k_to_xmajor<double>, grid, dim3(256), 0, st, (const double *)rows, gx, nx, nv, ld);
+    else hipLaunchKernelGGL(k_to_xmajor<float>, grid, dim3(256), 0, st, (const float *)rows, gx, nx, nv, ld);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------ diagnostics
 // E, J at interfaces, Phi = -<v g>, N = eps ||g||_2, remainder R at cells and
 // the kinetic-cell rule, for one state (rho, g).  LDS: 3*nx doubles.

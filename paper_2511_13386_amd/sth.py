@@ -31,7 +31,7 @@ EXPORTS = (
     "sth_fine_run", "sth_destroy", "sth_last_error", "sth_parareal_correct_batched", "sth_get_errors",
     "sth_graph_create", "sth_graph_launch", "sth_graph_wait", "sth_graph_destroy",
     "sth_fine_config_candidates", "sth_set_fine_config", "sth_get_fine_config",
-    "sth_coarse_sweep_batched", "sth_fine_sweep_chunk", "sth_fine_run_masks",
+    "sth_coarse_sweep_batched", "sth_fine_sweep_chunk", "sth_fine_run_masks", "sth_fine_run_noalloc",
 )
 
 
@@ -112,6 +112,8 @@ def lib() -> ctypes.CDLL:
                                    ctypes.POINTER(ctypes.c_int), _D, _VP]
         L.sth_fine_run_masks.argtypes = [_VP, _D, _D, ctypes.c_longlong, _VP, _VP, ctypes.c_longlong, _D, _D,
                                          ctypes.POINTER(ctypes.c_int), _D, _VP]
+        L.sth_fine_run_noalloc.argtypes = [_VP, _D, _D, ctypes.c_longlong, _D, _D,
+                                           ctypes.POINTER(ctypes.c_int), _D, _VP]
         L.sth_parareal_correct_batched.argtypes = [ctypes.POINTER(_VP), ctypes.c_int, _D, _VP]
         L.sth_get_errors.argtypes = [_VP, _D]
         L.sth_graph_create.argtypes = [ctypes.POINTER(_VP), ctypes.c_int, ctypes.POINTER(_VP)]
@@ -380,6 +382,21 @@ def sth_fine_run(p: Problem, rho_in, g_in, nsteps: int, stream=None):
     _check(lib().sth_fine_run(p.h, _d(rho_in), _d(g_arr), int(nsteps), _d(rho), _d(g),
                               mask.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), ctypes.byref(kin),
                               _stream(stream)))
+    return rho, g, mask, kin.value
+
+
+def sth_fine_run_noalloc(p: Problem, rho_in, g_in, nsteps: int, stream=None, want_g=True):
+    """sth_fine_run through the allocation-free entry point (static device
+    workspace); want_g=False passes no g_out."""
+    rho_in = np.ascontiguousarray(rho_in, dtype=np.float64)
+    g_arr = None if g_in is None else np.ascontiguousarray(g_in, dtype=np.float64)
+    rho = np.zeros(p.nx)
+    g = np.zeros((p.nx, p.nv)) if want_g else None
+    mask = np.zeros(p.nx, dtype=np.int32)
+    kin = ctypes.c_double()
+    _check(lib().sth_fine_run_noalloc(p.h, _d(rho_in), _d(g_arr), int(nsteps), _d(rho), _d(g),
+                                      mask.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), ctypes.byref(kin),
+                                      _stream(stream)))
     return rho, g, mask, kin.value
 
 

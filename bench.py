@@ -114,6 +114,8 @@ def parse():
     ap.add_argument("--budget-gib", type=float, default=8.0, help="serve: device arena for admission")
     ap.add_argument("--serve-chunk", type=int, default=256,
                     help="serve: fine steps per slice per tick (0: one parareal iteration per tick)")
+    ap.add_argument("--paper-steps-per-slice", type=int, default=50,
+                    help="1d3v/convergence: fine steps per slice of the paper setting (fine dt = 1/(200 S))")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB elementwise copy kernel (HBM counter calibration)")
     ap.add_argument("--other-iterations", type=int, default=8,
@@ -474,88 +476,155 @@ def run_serve(args, torch, sth, wl):
 def run_convergence(args, torch, sth, wl):
     """Parareal iterations to a successive error of 1e-10 against eps, with
     and without domain adaptation, in the paper's Section 5 setting (1D1V):
-    the convergence study of the paper's Section 5.1."""
+    the convergence study of the paper's Section 5.1, from the paper's
+    initial distribution with its micro part, with lifted (first and third
+    order) or carried slice starts, and with the implicit drift-diffusion
+    coarse propagator or the paper's explicit limit scheme S^0."""
     eps_list = [1e-7, 1e-6, 1e-5, 1e-4, 1e-3, 1e-2, 1e-1, 0.5, 1.0]
+    S = args.paper_steps_per_slice
     rows = []
     t0 = time.perf_counter()
     for mode, mode_name, L in ((sth.START_LIFT, "lift", 3), (sth.START_LIFT, "lift", 1),
                                (sth.START_CARRY, "carry", 1)):
-        for adapt in (False, True):
-            for eps in eps_list:
-                inst = wl.paper_setting(eps, adaptation=adapt, lift_order=L)
-                d = sth.Desc(nx=inst.nx, nv=inst.nv, eps_iface=inst.eps_iface, eps_cell=inst.eps_cell,
-                             rho0=inst.rho_in, T=inst.T, n_slices=inst.N, k_max=inst.N, tol=inst.tol,
-                             eta0=inst.eta0, delta0=inst.delta0, lift_order=inst.lift_order,
-                             start_mode=mode, cfl_theta=inst.theta,
-                             flags=sth.FIELD | (sth.HYBRID if adapt else 0), Lx=inst.Lx, vstar=inst.vstar)
-                p = sth.Problem(d)
-                try:
-                    errs = sth.parareal_solve(p, K=inst.N, tol=inst.tol)
-                    diverged = False
-                except sth.StHError as e:
-                    # the correction reported a non-finite density (the L = 3
-                    # lifting at eps ~ 1): the run is recorded as diverged
-                    if e.code != sth.STH_ENONFINITE:
-                        raise
-                    errs = sth.sth_get_errors(p) or [float("nan")]
-                    diverged = True
-                info = p.info()
-                rows.append({"start": mode_name, "lift_order": L, "adaptation": adapt, "eps": eps,
-                             "iterations": len(errs), "diverged": diverged,
-                             "final_err": errs[-1] if np.isfinite(errs[-1]) else None,
-                             "steps_per_slice": info.steps_per_slice,
-                             "kinetic_fraction": info.kinetic_iface_steps / max(
-                                 1.0, inst.nx * info.steps_per_slice * sum(inst.N - k for k in range(len(errs))))})
-                p.close()
+        for coarse, cflag in (("implicit", 0), ("explicit_S0", sth.COARSE_EXPLICIT)):
+            for adapt in (False, True):
+                for eps in eps_list:
+                    inst = wl.paper_setting(eps, adaptation=adapt, lift_order=L, micro=True)
+                    d = sth.Desc(nx=inst.nx, nv=inst.nv, eps_iface=inst.eps_iface, eps_cell=inst.eps_cell,
+                                 rho0=inst.rho_in, g0=inst.g_in, T=inst.T, n_slices=inst.N, k_max=inst.N,
+                                 tol=inst.tol, eta0=inst.eta0, delta0=inst.delta0, lift_order=inst.lift_order,
+                                 start_mode=mode, cfl_theta=inst.theta,
+                                 flags=sth.FIELD | cflag | (sth.HYBRID if adapt else 0), Lx=inst.Lx,
+                                 vstar=inst.vstar, steps_override=S)
+                    p = sth.Problem(d)
+                    try:
+                        errs = sth.parareal_solve(p, K=inst.N, tol=inst.tol)
+                        diverged = False
+                    except sth.StHError as e:
+                        # a correction reported a non-finite density (the L = 3
+                        # lifting at eps ~ 1): the run is recorded as diverged
+                        if e.code != sth.STH_ENONFINITE:
+                            raise
+                        errs = sth.sth_get_errors(p) or [float("nan")]
+                        diverged = True
+                    info = p.info()
+                    rows.append({"start": mode_name, "lift_order": L, "coarse": coarse, "adaptation": adapt,
+                                 "eps": eps, "iterations": len(errs), "diverged": diverged,
+                                 "final_err": errs[-1] if np.isfinite(errs[-1]) else None,
+                                 "steps_per_slice": info.steps_per_slice, "fine_dt": info.dt,
+                                 "kinetic_fraction": info.kinetic_iface_steps / max(
+                                     1.0, inst.nx * info.steps_per_slice * sum(inst.N - k for k in range(len(errs))))})
+                    p.close()
+            print(f"# convergence: {mode_name} L={L} {coarse} done", file=sys.stderr, flush=True)
     out = {"metric": "parareal iterations to successive error 1e-10 (convergence study)",
            "value": None, "unit": "iterations", "n_gpus": 1, "data": "synthetic",
-           "config": {"workload": "paper Section 5 setting in 1D1V: Nx=Nv=32, x*=2pi, v*=8, N_g=200, T_f=1, "
-                                  "eta0=delta0=1e-5, rho_in=3(1+0.9cos x), g'=0; slice starts lifted (L=3, L=1) or carried"},
+           "config": {"workload": ("paper Section 5 setting in 1D1V: Nx=Nv=32, x*=2pi, v*=8, N_g=200, T_f=1, "
+                                   "eta0=delta0=1e-5, initial distribution M(v) v^4 (1+0.9cos x) with its micro "
+                                   f"part, {S} fine steps per slice (fine dt {1.0 / (200 * S):.1e}); slice starts "
+                                   "lifted (L=3, L=1) or carried; coarse propagator implicit drift-diffusion or "
+                                   "the explicit limit scheme S^0")},
            "runs": rows, "wall_s": time.perf_counter() - t0}
     print(json.dumps(out), flush=True)
 
 
+# The paper's Table 3 (1D3V, 2 x 24-core Xeon Platinum 8268, OpenMP, 48
+# threads): wall-clock seconds per eps for parareal off/on x adaptation
+# off/on, and the fluid solver; context for the shape of the study only.
+TABLE3_S = {1.0: (96.1, 104.6, 42.38, 44.5), 1e-1: (96.1, 104.2, 35.2, 37.5), 1e-2: (96.1, 99.5, 31.1, 32.5),
+            1e-3: (96.1, 20.6, 17.0, 4.0), 1e-4: (96.1, 0.19, 13.0, 1.32)}
+TABLE3_FLUID_S = 0.25
+
+
 def run_1d3v(args, torch, sth, wl):
-    """The paper's 1D3V setting (Nx = 32, Nv = 32 x 16 x 16, N_g = 200,
-    T_f = 1, tol 1e-10, eta0 = delta0 = 1e-5): parareal iterations and wall
-    clock against eps, with and without domain adaptation, for states of
-    the form g(x, vx) M(vy) M(vz) (the initial data of the study has it)."""
+    """The paper's 1D3V study shape (Section 5, Table 3): Nx = 32, Nv = 32 x
+    16 x 16, N_g = 200, T_f = 1, tol 1e-10, eta0 = delta0 = 1e-5, the paper's
+    initial distribution with its micro part, for eps = 1 .. 1e-4: the serial
+    fine solver with and without domain adaptation, the parareal solve with
+    and without it (lifted slice starts, first order), with the implicit
+    drift-diffusion coarse propagator and with the paper's explicit limit
+    scheme S^0, and the coarse solver alone.  The fine step is the same for
+    every eps (as the equal serial times of Table 3 imply): T_f / (N_g S)."""
     eps_list = [1.0, 1e-1, 1e-2, 1e-3, 1e-4]
+    S = args.paper_steps_per_slice
     rows = []
     t0 = time.perf_counter()
-    for adapt in (False, True):
-        for eps in eps_list:
-            inst = wl.paper_setting(eps, adaptation=adapt, lift_order=1)
-            d = sth.Desc(nx=inst.nx, nv=inst.nv, eps_iface=inst.eps_iface, eps_cell=inst.eps_cell,
-                         rho0=inst.rho_in, T=inst.T, n_slices=inst.N, k_max=inst.N, tol=inst.tol,
-                         eta0=inst.eta0, delta0=inst.delta0, lift_order=1, start_mode=sth.START_LIFT,
-                         cfl_theta=inst.theta, flags=sth.FIELD | (sth.HYBRID if adapt else 0),
-                         Lx=inst.Lx, vstar=inst.vstar, nv_y=16, nv_z=16)
-            p = sth.Problem(d)
+    st = torch.cuda.Stream()
+
+    def desc(inst, N, steps, flags, K=1, tol=0.0):
+        return sth.Desc(nx=inst.nx, nv=inst.nv, eps_iface=inst.eps_iface, eps_cell=inst.eps_cell,
+                        rho0=inst.rho_in, g0=inst.g_in, T=inst.T, n_slices=N, k_max=K, tol=tol,
+                        eta0=inst.eta0, delta0=inst.delta0, lift_order=1, start_mode=sth.START_LIFT,
+                        cfl_theta=inst.theta, flags=flags, Lx=inst.Lx, vstar=inst.vstar, nv_y=16, nv_z=16,
+                        steps_override=steps)
+
+    for eps in eps_list:
+        inst = wl.paper_setting(eps, adaptation=True, lift_order=1, micro=True)
+        row = {"eps": eps}
+        # serial fine solver over T_f (one slice of N_g S steps)
+        for adapt in (False, True):
+            p = sth.Problem(desc(inst, 1, inst.N * S, sth.FIELD | (sth.HYBRID if adapt else 0)))
+            sth.sth_fine_run(p, inst.rho_in, inst.g_in, 10)  # warm
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-            errs = sth.parareal_solve(p, K=inst.N, tol=inst.tol)
+            _, _, _, kin = sth.sth_fine_run(p, inst.rho_in, inst.g_in, inst.N * S)
             torch.cuda.synchronize()
-            wall = time.perf_counter() - t1
-            info = p.info()
-            cells = info.kinetic_iface_steps * inst.nv
-            rows.append({"adaptation": adapt, "eps": eps, "iterations": len(errs), "final_err": errs[-1],
-                         "parareal_wall_s": wall, "steps_per_slice": info.steps_per_slice,
-                         "kinetic_cell_updates_vx": cells,
-                         "kinetic_cell_updates_3d_equivalent": cells * 16 * 16,
-                         "norm_scale": info.norm_scale})
+            row[f"serial_{'hybrid' if adapt else 'kinetic'}_s"] = time.perf_counter() - t1
+            row[f"serial_{'hybrid' if adapt else 'kinetic'}_kinetic_fraction"] = kin / (inst.nx * inst.N * S)
+            if not adapt:
+                row["fine_dt"] = p.info().dt
             p.close()
-            print(f"# 1d3v eps={eps:g} adaptation={adapt}: {len(errs)} iterations, {wall:.2f} s",
-                  file=sys.stderr, flush=True)
-    for r in rows:
-        if r["adaptation"]:
-            off = [q for q in rows if not q["adaptation"] and q["eps"] == r["eps"]][0]
-            r["wall_ratio_full_kinetic_over_hybrid"] = off["parareal_wall_s"] / r["parareal_wall_s"]
-    out = {"metric": "1D3V parareal iterations and wall clock against eps (paper's Table 3 shape)",
+        for coarse, cflag in (("implicit", 0), ("explicit_S0", sth.COARSE_EXPLICIT)):
+            # the coarse solver alone over the N_g slices
+            p = sth.Problem(desc(inst, inst.N, S, sth.FIELD | cflag))
+            sth.sth_coarse_sweep(p, st)
+            torch.cuda.synchronize()
+            p.close()
+            p = sth.Problem(desc(inst, inst.N, S, sth.FIELD | cflag))
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            sth.sth_coarse_sweep(p, st)
+            torch.cuda.synchronize()
+            row[f"fluid_{coarse}_s"] = time.perf_counter() - t1
+            p.close()
+            for adapt in (False, True):
+                p = sth.Problem(desc(inst, inst.N, S, sth.FIELD | cflag | (sth.HYBRID if adapt else 0),
+                                     K=inst.N, tol=inst.tol))
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                try:
+                    errs = sth.parareal_solve(p, K=inst.N, tol=inst.tol, stream=st)
+                    div = False
+                except sth.StHError as e:
+                    if e.code != sth.STH_ENONFINITE:
+                        raise
+                    errs, div = sth.sth_get_errors(p) or [float("nan")], True
+                torch.cuda.synchronize()
+                key = f"parareal_{coarse}_{'hybrid' if adapt else 'kinetic'}"
+                row[key + "_s"] = time.perf_counter() - t1
+                row[key + "_iterations"] = len(errs)
+                row[key + "_diverged"] = div
+                p.close()
+        base = row["serial_kinetic_s"]
+        for k in list(row):
+            if k.endswith("_s"):
+                row[k[:-2] + "_speedup"] = base / row[k]
+        t3 = TABLE3_S[eps]
+        row["paper_table3_s"] = {"para_off_adapt_off": t3[0], "para_off_adapt_on": t3[1],
+                                 "para_on_adapt_off": t3[2], "para_on_adapt_on": t3[3],
+                                 "fluid": TABLE3_FLUID_S}
+        row["paper_table3_speedup"] = {k: t3[0] / v for k, v in row["paper_table3_s"].items()}
+        rows.append(row)
+        print(f"# 1d3v eps={eps:g}: serial {base:.3f} s, parareal (implicit G, hybrid) "
+              f"{row['parareal_implicit_hybrid_s']:.3f} s in {row['parareal_implicit_hybrid_iterations']} "
+              f"iterations", file=sys.stderr, flush=True)
+    out = {"metric": "1D3V Table-3 shape: wall clock and speedups against the serial full-kinetic fine solver",
            "value": None, "unit": "s", "n_gpus": 1, "data": "synthetic",
-           "config": {"workload": "Nx=32, Nv=32x16x16 (states g(x,vx)M(vy)M(vz), advanced through their vx "
-                                  "factor), x*=2pi, v*=8, N_g=200, T_f=1, tol 1e-10, eta0=delta0=1e-5, "
-                                  "rho_in=3(1+0.9cos x), g'=0, lifted slice starts (L=1), FP64"},
+           "config": {"workload": ("Nx=32, Nv=32x16x16 (states g(x,vx)M(vy)M(vz), advanced through their vx "
+                                   "factor), x*=2pi, v*=8, N_g=200, T_f=1, tol 1e-10, eta0=delta0=1e-5, "
+                                   "initial distribution M(v) vx^4 (1+0.9cos x) with its micro part, lifted "
+                                   f"slice starts (L=1), FP64, {S} fine steps per slice (fine dt "
+                                   f"{1.0 / (200 * S):.1e}, the same for every eps)"),
+                      "paper_hardware": "2x Xeon Platinum 8268, 48 OpenMP threads (context only)"},
            "runs": rows, "wall_s": time.perf_counter() - t0}
     print(json.dumps(out), flush=True)
 

@@ -160,19 +160,43 @@ def poisson_arrivals(n: int, rate: float, seed: int = 99) -> np.ndarray:
 
 
 def paper_setting(eps: float, adaptation: bool = True, nx: int = 32, nv: int = 32, N: int = 200,
-                  T: float = 1.0, lift_order: int = 3) -> Instance:
+                  T: float = 1.0, lift_order: int = 3, micro: bool = False) -> Instance:
     """The numerical setting of the paper's Section 5 in 1D1V: torus length
     2 pi, v* = 8, Nx = Nvx = 32, N_g = 200 slices, T_f = 1, thresholds
-    eta0 = delta0 = 1e-5, lifting order 3, constant eps.  Initial density
-    3 (1 + 0.9 cos(x)), the density of the paper's far-from-equilibrium
-    initial condition (<v^4 M> = 3), started at local equilibrium (g' = 0)."""
+    eta0 = delta0 = 1e-5, lifting order 3, constant eps.  micro=False: the
+    density 3 (1 + 0.9 cos(x)) of the paper's initial condition (<v^4 M> = 3)
+    at local equilibrium (g' = 0).  micro=True: the paper's initial
+    distribution itself (see paper_initial_distribution), with its density
+    and its micro part g' = (f - rho M)/eps."""
     Lx = 2 * math.pi
     xc = cell_centres(nx, Lx)
-    return Instance(nx=nx, nv=nv, rho_in=3.0 * (1.0 + 0.9 * np.cos(2 * math.pi * xc / Lx)),
+    rho = 3.0 * (1.0 + 0.9 * np.cos(2 * math.pi * xc / Lx))
+    g_in = None
+    if micro:
+        rho, g_in = paper_initial_distribution(nx, nv, eps, Lx=Lx, vstar=8.0)
+    return Instance(nx=nx, nv=nv, rho_in=rho, g_in=g_in,
                     eps_iface=np.full(nx, eps), eps_cell=np.full(nx, eps), T=T, N=N, K=N,
                     tol=1e-10, theta=1.0, vstar=8.0, Lx=Lx, eta0=1e-5, delta0=1e-5,
                     hybrid=adaptation, lift_order=lift_order,
-                    name=f"paper-setting-eps{eps:.0e}-{'adapt' if adaptation else 'noadapt'}")
+                    name=f"paper-setting-eps{eps:.0e}-{'adapt' if adaptation else 'noadapt'}"
+                         f"{'-micro' if micro else ''}")
+
+
+def paper_initial_distribution(nx: int, nv: int, eps: float, Lx: float = 2 * math.pi, vstar: float = 8.0):
+    """The initial distribution of the paper's Section 5 on the grid nodes,
+    f(x, v) = M(v) v^4 (1 + 0.9 cos(2 pi x / Lx)) with M(v) = exp(-v^2/2)/sqrt(2 pi)
+    (for the 1D3V statement this is the vx factor of f; the transverse
+    factors are M(vy) M(vz)), at cell centres and midpoint velocity nodes.
+    Returns the density rho_i = sum_j f_ij dv and the scaled perturbation
+    g'_ij = (f_ij - rho_i M_j)/eps, x-major."""
+    xc = cell_centres(nx, Lx)
+    dv = 2.0 * vstar / nv
+    v = -vstar + (np.arange(nv) + 0.5) * dv
+    M = np.exp(-0.5 * v * v) / math.sqrt(2.0 * math.pi)
+    f = (1.0 + 0.9 * np.cos(2 * math.pi * xc / Lx))[:, None] * (M * v ** 4)[None, :]
+    rho = f.sum(axis=1) * dv
+    g = (f - rho[:, None] * M[None, :]) / eps
+    return rho, g
 
 
 def small_hybrid(seed: int = 0, nx: int = 96, nv: int = 32, N: int = 4, T: float = 2e-3,

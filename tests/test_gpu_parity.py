@@ -19,6 +19,9 @@ pytestmark = pytest.mark.gpu
 
 RHO64, G64 = 1e-12, 1e-10
 RHO32, G32 = 2e-6, 2e-4
+# FP32 bulk over the batching workload's slices with adaptation: the stated
+# FP32-bulk tolerances, or four times the binary32-storage floor
+RHO32_C4, G32_C4 = 1e-5, 1e-3
 
 
 def _fine_pair(orc, inst, nsteps, precision=sth.FP64, g_in=None):
@@ -547,5 +550,89 @@ def test_config4_instances_in_one_batched_sweep(orc, precision):
             if n == 1:
                 sth.sth_parareal_correct(p)
                 assert rel_err(sth.sth_get_rho(p)[1], ro) < tol_r, (inst.nx, inst.nv)
+    for p in ps:
+        p.close()
+
+
+@pytest.mark.parametrize("eps,explicit", [(1e-2, False), (1.0, True), (1e-4, True)])
+def test_paper_initial_distribution_parareal(orc, eps, explicit):
+    """The paper's Section 5 setting from its initial distribution
+    M(v) v^4 (1 + 0.9 cos x) with the micro part g' = (f - rho M)/eps, a fixed
+    fine step (20 per slice), lifted slice starts (Algorithm 1), adaptation
+    on, with the implicit or the explicit (S^0) coarse propagator: slice
+    values and successive errors against the oracle."""
+    S = 20
+    inst = wl.paper_setting(eps, adaptation=True, lift_order=1, micro=True, N=8, T=0.04)
+    inst.K = 3
+    cflag = sth.COARSE_EXPLICIT if explicit else 0
+    d = desc_of(inst, start_mode=sth.START_LIFT, steps_override=S)
+    d.flags |= cflag
+    p = sth.Problem(d)
+    po, _, dtG = oracle_of(orc, inst, start_mode=orc.START_LIFT)
+    po.flags |= (orc.COARSE_EXPLICIT if explicit else 0)
+    po.dt = (inst.T / inst.N) / S
+    assert abs(p.info().dt - po.dt) < 1e-15 * po.dt
+    errs = sth.parareal_solve(p, K=inst.K, fixed_iterations=True)
+    U = sth.sth_get_rho(p)
+    Uo, erro, it, kin = orc.parareal(po, inst.eps_iface, inst.eps_cell, inst.N, S, dtG, inst.K, 0.0,
+                                     inst.rho_in, g_in=inst.g_in)
+    print(f"paper setting eps={eps:g} {'S0' if explicit else 'implicit'} coarse: slice values "
+          f"{rel_err(U, Uo):.2e} from the oracle's, kinetic {p.info().kinetic_iface_steps:.0f} vs {kin:.0f}",
+          flush=True)
+    # lifted starts at dx = 2 pi/32 (the third-derivative amplification of the
+    # lifted-start tests is far smaller at this coarse grid)
+    assert rel_err(U, Uo) < 1e-11
+    assert np.allclose(errs, erro, rtol=1e-8, atol=1e-14)
+    assert p.info().kinetic_iface_steps == kin
+    p.close()
+
+
+def test_config4_fp32_bulk_with_adaptation(orc):
+    """FP32 bulk with domain adaptation at the batching workload's sizes: the
+    five kernel classes above swept together in one batched call; slice 1 of
+    each instance (the same start on both sides) equals the single-slice run
+    of the same kernel class bit for bit, and, with the FP64 oracle's status
+    history imposed, the oracle within the FP32-bulk tolerance (rho 1e-5 and
+    g' 1e-3, or four times the binary32-storage floor the oracle measures);
+    the (step, cell) decisions taken differently are counted."""
+    seeds = [1034, 1022, 1004, 1021, 1027]
+    insts, descs = [], []
+    for sd in seeds:
+        inst = wl.random_instance(sd, N=32, T=0.01)
+        inst.hybrid = True
+        d = desc_of(inst, precision=sth.FP32_BULK, start_mode=sth.START_CARRY, lift_order=1, K=1)
+        probe = sth.Problem(d)
+        scale = 150.0 / probe.info().steps_per_slice
+        probe.close()
+        inst.T *= scale
+        insts.append(inst)
+        descs.append(desc_of(inst, precision=sth.FP32_BULK, start_mode=sth.START_CARRY, lift_order=1, K=1))
+    ps = [sth.Problem(d) for d in descs]
+    sth.sth_coarse_sweep_batched(ps)
+    sth.sth_fine_sweep_batched(ps)
+    for inst, p in zip(insts, ps):
+        po, ns, _ = orc.setup(inst.nx, inst.nv, inst.eps_iface, inst.rho_in, T=inst.T, N=inst.N,
+                              theta=inst.theta, Lx=inst.Lx, vstar=inst.vstar, eta0=inst.eta0,
+                              delta0=inst.delta0, flags=orc.FIELD | orc.HYBRID, lift_order=1,
+                              start_mode=orc.START_CARRY)
+        assert p.info().steps_per_slice == ns
+        ro, go, _, _, ho = orc.fine_propagate_masks(po, inst.eps_iface, inst.eps_cell, inst.rho_in, None, ns)
+        q = type(po).from_buffer_copy(po)
+        q.flags |= orc.STORE_F32
+        rf, gf, _, _, _ = orc.fine_propagate_masks(q, inst.eps_iface, inst.eps_cell, inst.rho_in, None, ns,
+                                                  replay=ho)
+        rt = max(RHO32_C4, 4.0 * rel_err(rf, ro))
+        gt = max(G32_C4, 4.0 * rel_err(gf, go))
+        # the batched slice 1 is the single-slice run of the same class
+        g_batched = sth.sth_get_g(p, 1)
+        sth.sth_parareal_correct(p)
+        r_batched = sth.sth_get_rho(p)[1]
+        r1, g1, _, _, h1 = sth.sth_fine_run_masks(p, inst.rho_in, None, ns)
+        assert np.array_equal(r1, r_batched) and np.array_equal(g1, g_batched), (inst.nx, inst.nv)
+        r2, g2, _, _, _ = sth.sth_fine_run_masks(p, inst.rho_in, None, ns, replay=ho)
+        print(f"{inst.nx}x{inst.nv} eps {inst.eps_iface[0]:.1e}: {int(np.sum(h1 != ho))} of {ho.size} states "
+              f"differ; history imposed rho {rel_err(r2, ro):.2e} (tol {rt:.1e}), g' {rel_err(g2, go):.2e} "
+              f"(tol {gt:.1e})", flush=True)
+        assert rel_err(r2, ro) < rt and rel_err(g2, go) < gt, (inst.nx, inst.nv)
     for p in ps:
         p.close()

@@ -336,7 +336,8 @@ def batch_block(args, torch, sth, wl, prec, K, with_graph):
     return {
         "metric": "batched fine-sweep kinetic cell-updates/s (independent instances, mixed sizes)",
         "value": rate, "unit": "cell-updates/s", "n_gpus": 1, "steps": K, "warmup": args.warmup,
-        "ms_per_step": float(np.mean(ms)), "higher_is_better": True, "scaling": "weak",
+        "ms_per_step": float(np.mean(ms)), "sweep_ms_per_iteration": [round(m, 1) for m in ms],
+        "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64" if prec == sth.FP64 else "f32-bulk/f64-macro",
         "data": "synthetic",
         "config": {"workload": (f"{len(insts)} instances seed 1000+i, Nx in {{128..2048}}, Nv in {{32,64,128}}, "
@@ -381,6 +382,13 @@ def run_serve(args, torch, sth, wl):
 
     budget = int(args.budget_gib * (1 << 30))
     chunk = args.serve_chunk if args.serve_chunk > 0 else None
+    last = [0]
+
+    def progress(n):
+        if n // 250 > last[0] // 250 or n == R:
+            print(f"# served {n}/{R}", file=sys.stderr, flush=True)
+        last[0] = n
+
     srv = serving.Server(budget, chunk_steps=chunk)
     # warmup: every kernel class once
     warm = [serving.Request(r, desc(i, sth.FP32_BULK), 0.0, 1) for r, i in enumerate(insts[:48])]
@@ -392,7 +400,8 @@ def run_serve(args, torch, sth, wl):
     # saturated throughput: everything arrives at once
     reqs = [serving.Request(r, desc(i, sth.FP32_BULK), 0.0, K) for r, i in enumerate(insts)]
     t0 = time.perf_counter()
-    sat = srv.run(reqs)
+    last[0] = 0
+    sat = srv.run(reqs, on_done=progress)
     sat_wall = time.perf_counter() - t0
     sat_rate = R / sat_wall
     print(f"# saturated: {R} requests in {sat_wall:.2f} s", file=sys.stderr, flush=True)
@@ -403,7 +412,8 @@ def run_serve(args, torch, sth, wl):
     reqs = [serving.Request(r, desc(i, sth.FP32_BULK), float(arr[r]), K) for r, i in enumerate(insts)]
     t0 = time.perf_counter()
     ticks0 = srv.ticks
-    res = srv.run(reqs)
+    last[0] = 0
+    res = srv.run(reqs, on_done=progress)
     wall = time.perf_counter() - t0
     ticks = srv.ticks - ticks0
     pct = serving.latency_percentiles(res)

@@ -186,13 +186,18 @@ int release_table(int slot, hipStream_t st)
     return STH_OK;
 }
 
-// Side streams of a device for batches with several kernel classes: the
-// classes run concurrently, forked from and joined back into the caller's
-// stream with events (default priority, non-blocking).
-constexpr int kSideStreams = 3;
+// Lanes of a device for batches with several kernel classes: each class
+// runs on one of kLanes streams, forked from and joined back into the
+// caller's stream with events.  Classes on one hardware queue run one after
+// the other, and plain streams share the process's few hardware queues with
+// every other stream in use (the caller's among them), so the lanes are
+// created with a CU mask of every CU: a mask belongs to a hardware queue, and
+// a masked stream gets a queue of its own.  Where the runtime refuses a
+// masked stream, the lane is an ordinary non-blocking stream.
+constexpr int kLanes = 4;
 struct SidePool {
-    hipStream_t s[kSideStreams] = {};
-    hipEvent_t fork = nullptr, join[kSideStreams] = {};
+    hipStream_t s[kLanes] = {};
+    hipEvent_t fork = nullptr, join[kLanes] = {};
     bool ready = false;
 };
 std::mutex g_side_mu, g_side_issue_mu;
@@ -206,8 +211,15 @@ int side_pool(SidePool **out)
     if ((int)g_side.size() <= dev) g_side.resize(dev + 1);
     SidePool &P = g_side[dev];
     if (!P.ready) {
-        for (int i = 0; i < kSideStreams; ++i) {
-            HIPCHK(hipStreamCreateWithFlags(&P.s[i], hipStreamNonBlocking));
+        int cus = 0;
+        HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        std::vector<uint32_t> mask((size_t)std::max(1, (cus + 31) / 32), 0u);
+        for (int c = 0; c < cus; ++c) mask[(size_t)c / 32] |= 1u << (c % 32);
+        for (int i = 0; i < kLanes; ++i) {
+            if (hipExtStreamCreateWithCUMask(&P.s[i], (uint32_t)mask.size(), mask.data()) != hipSuccess) {
+                (void)hipGetLastError();
+                HIPCHK(hipStreamCreateWithFlags(&P.s[i], hipStreamNonBlocking));
+            }
             HIPCHK(hipEventCreateWithFlags(&P.join[i], hipEventDisableTiming));
         }
         HIPCHK(hipEventCreateWithFlags(&P.fork, hipEventDisableTiming));
@@ -512,8 +524,9 @@ void sort_items(std::vector<SweepItem> &items)
 }
 
 // Launch the sorted units (device table dtab, same order): one launch per
-// kernel class; with several classes the costliest runs on st and the others
-// on the side streams, all concurrent, joined back into st.
+// kernel class.  With several classes, each goes to the lane with the least
+// work so far, costliest class first (longest-processing-time order), all
+// lanes concurrent and joined back into st.
 int issue_classes(const std::vector<SweepItem> &items, FineUnit *dtab, hipStream_t st)
 {
     struct Group {
@@ -548,15 +561,18 @@ int issue_classes(const std::vector<SweepItem> &items, FineUnit *dtab, hipStream
     if (rc) return rc;
     // the fork/join events are shared: issue one batch at a time
     std::lock_guard<std::mutex> lk(g_side_issue_mu);
-    const int nside = std::min<int>(kSideStreams, (int)groups.size() - 1);
+    const int nlanes = std::min<int>(kLanes, (int)groups.size());
+    double load[kLanes] = {};
     HIPCHK(hipEventRecord(P->fork, st));
-    for (int i = 0; i < nside; ++i) HIPCHK(hipStreamWaitEvent(P->s[i], P->fork, 0));
-    for (size_t g = 0; g < groups.size(); ++g) {
-        const int lane = (int)(g % (size_t)(nside + 1));
-        hipStream_t gs = lane == 0 ? st : P->s[lane - 1];
-        HIPCHK(launch_fine(groups[g].sh, dtab + groups[g].begin, (int)(groups[g].end - groups[g].begin), gs));
+    for (int i = 0; i < nlanes; ++i) HIPCHK(hipStreamWaitEvent(P->s[i], P->fork, 0));
+    for (const Group &g : groups) {
+        int lane = 0;
+        for (int i = 1; i < nlanes; ++i)
+            if (load[i] < load[lane]) lane = i;
+        load[lane] += g.cost;
+        HIPCHK(launch_fine(g.sh, dtab + g.begin, (int)(g.end - g.begin), P->s[lane]));
     }
-    for (int i = 0; i < nside; ++i) {
+    for (int i = 0; i < nlanes; ++i) {
         HIPCHK(hipEventRecord(P->join[i], P->s[i]));
         HIPCHK(hipStreamWaitEvent(st, P->join[i], 0));
     }

@@ -31,7 +31,7 @@ from __future__ import annotations
 
 import time
 from dataclasses import dataclass, field
-from typing import Dict, List, Optional
+from typing import Callable, Dict, List, Optional
 
 import numpy as np
 
@@ -152,9 +152,11 @@ class Server:
         sth.sth_coarse_sweep(prob, self.stream)
         return _Active(req, prob, off, size, now)
 
-    def run(self, requests: List[Request], clock=time.perf_counter) -> List[Result]:
+    def run(self, requests: List[Request], clock=time.perf_counter,
+            on_done: Optional[Callable[[int], None]] = None) -> List[Result]:
         """Serve the requests (sorted by arrival) in real time; returns one
-        result per request."""
+        result per request.  on_done(n) is called with the number of finished
+        requests after each tick that finished some."""
         pending = sorted(requests, key=lambda r: r.arrival)
         waiting: List[Request] = []
         active: List[_Active] = []
@@ -205,6 +207,8 @@ class Server:
                     self.arena.release(a.off, a.size)
                 else:
                     still.append(a)
+            if on_done is not None and len(still) < len(active):
+                on_done(len(results))
             active = still
         return [results[r.rid] for r in requests]
 

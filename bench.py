@@ -91,7 +91,7 @@ def parse():
     ap.add_argument("--no-other-precision", action="store_true",
                     help="config2: skip the same solve in the other precision")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--workload", choices=["config2", "batch", "serve", "convergence", "1d3v", "unit"],
+    ap.add_argument("--workload", choices=["config2", "batch", "serve", "convergence", "linf", "1d3v", "unit"],
                     default="config2",
                     help="config2: the hybrid parareal problem the metric is quoted on; "
                          "batch: many independent instances in one batched sweep per iteration")
@@ -537,6 +537,106 @@ def run_convergence(args, torch, sth, wl):
     print(json.dumps(out), flush=True)
 
 
+def run_linf(args, torch, sth, wl):
+    """Distance over time of the multiscale solutions from the classical
+    one (Section 5.1, the L-infinity comparison): the classical scheme is the
+    fine scheme without parareal or domain adaptation, run from t = 0 to
+    every sampled slice end; against it, the sequential hybrid run (domain
+    adaptation, no parareal) and the converged parareal solutions (successive
+    error 1e-10) with lifted slice starts of order L = 1, 2, 3 and with
+    carried starts, with and without adaptation, for eps = 0.5 and 1e-4 in
+    the paper's Section 5 setting (1D1V, the paper's initial distribution
+    with its micro part, 50 fine steps per slice, implicit coarse G)."""
+    S = args.paper_steps_per_slice
+    every = 5
+    rows = []
+    t0 = time.perf_counter()
+    for eps in (0.5, 1e-4):
+        inst = wl.paper_setting(eps, adaptation=False, lift_order=1, micro=True)
+        N = inst.N
+        samples = list(range(every, N + 1, every))
+
+        def desc(flags, lift_order=1, start_mode=sth.START_LIFT, n_slices=N, K=N, tol=inst.tol):
+            return sth.Desc(nx=inst.nx, nv=inst.nv, eps_iface=inst.eps_iface, eps_cell=inst.eps_cell,
+                            rho0=inst.rho_in, g0=inst.g_in, T=inst.T, n_slices=n_slices, k_max=K, tol=tol,
+                            eta0=inst.eta0, delta0=inst.delta0, lift_order=lift_order, start_mode=start_mode,
+                            cfl_theta=inst.theta, flags=flags, Lx=inst.Lx, vstar=inst.vstar, steps_override=S)
+
+        def serial(flags):
+            # from t = 0 to every sampled slice end, one fine run each
+            p = sth.Problem(desc(flags))
+            out = {}
+            for n in samples:
+                out[n] = sth.sth_fine_run(p, inst.rho_in, inst.g_in, n * S)[0]
+            p.close()
+            return out
+
+        classical = serial(sth.FIELD)
+        scale = max(float(np.max(np.abs(c))) for c in classical.values())
+
+        def dist(U):
+            return max(float(np.max(np.abs(U[n] - classical[n]))) for n in samples)
+
+        hybrid = serial(sth.FIELD | sth.HYBRID)
+        row = {"eps": eps, "density_scale": scale, "sequential_hybrid": dist(hybrid), "parareal": []}
+        for start, L in (("lift", 1), ("lift", 2), ("lift", 3), ("carry", 1)):
+            for adapt in (False, True):
+                mode = sth.START_LIFT if start == "lift" else sth.START_CARRY
+                p = sth.Problem(desc(sth.FIELD | (sth.HYBRID if adapt else 0), lift_order=L, start_mode=mode))
+                try:
+                    errs = sth.parareal_solve(p, K=N, tol=inst.tol)
+                    bad = False
+                except sth.StHError as e:
+                    if e.code != sth.STH_ENONFINITE:
+                        raise
+                    errs, bad = sth.sth_get_errors(p) or [float("nan")], True
+                U = sth.sth_get_rho(p)
+                p.close()
+                conv = (not bad) and errs[-1] < inst.tol
+                row["parareal"].append({
+                    "start": start, "lift_order": L, "adaptation": adapt, "iterations": len(errs),
+                    "converged": conv, "final_err": errs[-1] if np.isfinite(errs[-1]) else None,
+                    "linf_vs_classical": dist(U) if not bad else None})
+        rows.append(row)
+        print(f"# linf eps={eps:g} done", file=sys.stderr, flush=True)
+    # the printed variants of the hybrid scheme, sequential runs to T_f:
+    # the cell-wise density update (not conservative, Section 3.3 remark)
+    # and the criterion on |R| without eps^2, against the defaults
+    variants = []
+    for eps in (0.5, 1e-1, 1e-2, 1e-3, 1e-4, 1e-5, 1e-6):
+        inst = wl.paper_setting(eps, adaptation=True, lift_order=1, micro=True)
+        m0 = float(np.sum(inst.rho_in))
+        ns = inst.N * S
+        res = {}
+        for name, flags in (("classical", sth.FIELD), ("hybrid", sth.FIELD | sth.HYBRID),
+                            ("hybrid_cellwise_update", sth.FIELD | sth.HYBRID | sth.LITERAL_FLUX),
+                            ("hybrid_criterion_abs_R", sth.FIELD | sth.HYBRID | sth.LITERAL_R)):
+            d = sth.Desc(nx=inst.nx, nv=inst.nv, eps_iface=inst.eps_iface, eps_cell=inst.eps_cell,
+                         rho0=inst.rho_in, g0=inst.g_in, T=inst.T, n_slices=inst.N, k_max=1, tol=0.0,
+                         eta0=inst.eta0, delta0=inst.delta0, lift_order=1, start_mode=sth.START_LIFT,
+                         cfl_theta=inst.theta, flags=flags, Lx=inst.Lx, vstar=inst.vstar, steps_override=S)
+            p = sth.Problem(d)
+            r, _, _, kin = sth.sth_fine_run(p, inst.rho_in, inst.g_in, ns)
+            p.close()
+            res[name] = (r, kin / (inst.nx * ns))
+        c = res["classical"][0]
+        v = {"eps": eps}
+        for name in ("hybrid", "hybrid_cellwise_update", "hybrid_criterion_abs_R"):
+            r, kf = res[name]
+            v[name] = {"linf_vs_classical_at_T": float(np.max(np.abs(r - c))),
+                       "mass_drift_rel": float(abs(np.sum(r) - m0) / abs(m0)), "kinetic_fraction": kf}
+        variants.append(v)
+    print("# linf variants done", file=sys.stderr, flush=True)
+    out = {"metric": "L-infinity distance over time from the classical scheme (Section 5.1)",
+           "value": None, "unit": "density", "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": ("paper Section 5 setting in 1D1V: Nx=Nv=32, x*=2pi, v*=8, N_g=200, T_f=1, "
+                                   "eta0=delta0=1e-5, initial distribution M(v) v^4 (1+0.9cos x) with its micro "
+                                   f"part, {S} fine steps per slice, implicit coarse G, parareal to successive "
+                                   f"error 1e-10; distances over every {every}-th slice end, FP64")},
+           "runs": rows, "hybrid_variants_at_T": variants, "wall_s": time.perf_counter() - t0}
+    print(json.dumps(out), flush=True)
+
+
 # The paper's Table 3 (1D3V, 2 x 24-core Xeon Platinum 8268, OpenMP, 48
 # threads): wall-clock seconds per eps for parareal off/on x adaptation
 # off/on, and the fluid solver; context for the shape of the study only.
@@ -778,6 +878,9 @@ def main():
         return
     if args.workload == "1d3v":
         run_1d3v(args, torch, sth, wl)
+        return
+    if args.workload == "linf":
+        run_linf(args, torch, sth, wl)
         return
     if args.workload == "unit":
         run_unit(args, torch, sth, wl)

@@ -71,6 +71,28 @@ def measured_traffic(workload_key):
         return None
 
 
+def measured_batch_traffic():
+    """Counted HBM bytes of the first batched sweep of the 256-instance FP32
+    batch and its algorithmic bytes, from the committed counter summary, if it
+    was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "k_fine_batch256_fp32_hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_sources_sha256") != sources_sha256():
+        return None
+    try:
+        return (float(kv["first_sweep_fetch_bytes"]) + float(kv["first_sweep_write_bytes"]),
+                float(kv["first_sweep_algorithmic_bytes"]))
+    except (KeyError, ValueError):
+        return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -333,6 +355,9 @@ def batch_block(args, torch, sth, wl, prec, K, with_graph):
         errs.append(float(np.max(np.abs(U_batch[i] - U1)) / np.max(np.abs(U1))))
         p1.close()
     rate1 = kin1 / (ms1 * 1e-3)
+    # the counter summary covers the FP32 batch workload of the defaults
+    bt = (measured_batch_traffic() if prec == sth.FP32_BULK and args.batch_count == 256
+          and args.batch_slices == 32 and args.batch_T == 0.01 else None)
     return {
         "metric": "batched fine-sweep kinetic cell-updates/s (independent instances, mixed sizes)",
         "value": rate, "unit": "cell-updates/s", "n_gpus": 1, "steps": K, "warmup": args.warmup,
@@ -348,9 +373,12 @@ def batch_block(args, torch, sth, wl, prec, K, with_graph):
                                  "instances": len(U_batch),
                                  "sample": f"every {args.baseline_every}-th instance, alone, FP64"},
         "roofline": {"bound": "hbm", "achieved": alg_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": alg_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "frac": alg_gbs / HBM_PEAK_GBS, "traffic": bt[0] if bt else None,
                      "achieved_kind": ("algorithmic bytes: read and write of g' per kinetic cell-update "
-                                       "plus 64 B per kinetic interface-step, over the sweep time")},
+                                       "plus 64 B per kinetic interface-step, over the sweep time"),
+                     "traffic_kind": ("counted HBM bytes (FETCH_SIZE + WRITE_SIZE) of the first iteration's "
+                                      "sweep, all kernel classes"),
+                     "traffic_over_algorithmic_same_sweep": (bt[0] / bt[1]) if bt else None},
         "speedup_vs_single_fp64": rate / rate1,
         "max_rel_rho_diff_vs_single_fp64": max(errs) if errs else None,
         "mass_drift_rel_max": mass,
@@ -1012,6 +1040,7 @@ def main():
         alg2 = [kin * inst.nv * 2 * realsz2 + it * MACRO_BYTES_PER_IFACE_STEP
                 for kin, it in zip(q["kin_iter"], iface2)]
         gbs2 = float(np.mean([b / (ms * 1e-3) for b, ms in zip(alg2, ms2)])) / 1e9
+        traffic2 = measured_traffic(f"{inst.nx}x{inst.nv}_{'fp32' if prec2 == sth.FP32_BULK else 'fp64'}")
         out[key] = {
             "value": v2, "unit": "cell-updates/s (over the fine sweeps)",
             "iterations": K2,
@@ -1020,8 +1049,9 @@ def main():
             "fine_step_us": float(np.mean(ms2)) * 1e3 / q["info"].steps_per_slice,
             "parareal_wall_s": q["wall"],
             "roofline": {"bound": "hbm", "achieved": gbs2, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": gbs2 / HBM_PEAK_GBS, "traffic": None,
-                         "achieved_kind": "algorithmic (equivalent) bytes, as the main roofline"},
+                         "frac": gbs2 / HBM_PEAK_GBS, "traffic": traffic2,
+                         "achieved_kind": "algorithmic (equivalent) bytes, as the main roofline",
+                         "counted_hbm_gbs": (traffic2 / (float(np.mean(ms2)) * 1e-3) / 1e9) if traffic2 else None},
             "first_slice_max_rel_rho_diff": float(np.max(np.abs(q["first_slice"] - r["first_slice"]))
                                                   / np.max(np.abs(r["first_slice"]))),
             "first_slice_note": ("slice 1 after one iteration is one fine propagation of 369,148 steps from "

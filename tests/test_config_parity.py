@@ -116,6 +116,27 @@ def test_config2_slice1_full_length(orc):
     p32.close()
 
 
+def test_config2_first_sweep_in_the_bench_launch():
+    """The benchmark's launch, the first batched sweep of all 64 slices of
+    the 512 x 64 workload in one launch (FP64, carried starts), gives slice 1
+    bit for bit the single-slice run that the full-length test above holds
+    to the oracle."""
+    inst = wl.config2()
+    p = sth.Problem(desc_of(inst, precision=sth.FP64, lift_order=1, K=1))
+    ns = p.info().steps_per_slice
+    assert ns == 369148
+    sth.sth_coarse_sweep(p)
+    sth.sth_fine_sweep_batched([p])
+    g_b = sth.sth_get_g(p, 1)
+    sth.sth_parareal_correct(p, want_err=False)
+    r_b = sth.sth_get_rho(p)[1]
+    r1, g1, _, _ = sth.sth_fine_run(p, inst.rho_in, None, ns)
+    print(f"512x64 first sweep: slice 1 rho max diff {np.max(np.abs(r_b - r1)):.1e}, "
+          f"g' max diff {np.max(np.abs(g_b - g1)):.1e}", flush=True)
+    assert np.array_equal(r_b, r1) and np.array_equal(g_b, g1)
+    p.close()
+
+
 def test_config3_three_full_slices(orc):
     """2048 x 128 at T = 1/64: slices 1, 2 and 65 of the first sweep, 13,747
     steps each, FP64 and FP32 bulk."""

@@ -200,7 +200,14 @@ int  sth_coarse_sweep_batched(sth_problem *const *p, int count, void *stream);
 /* Fine propagator F = S^HMM (scheme of Section 2.3 with the cell rules of
  * Section 2.2) over every unconverged slice n > k of every problem in the
  * batch, all in one batched launch per kernel class: the parallel loop of
- * Algorithm 1.  Slice-start perturbations follow start_mode. */
+ * Algorithm 1.  Slice-start perturbations follow start_mode.  Asynchronous
+ * on `stream`: with several kernel classes the launches run concurrently on
+ * four library streams of the current device (created once per process,
+ * each with a CU mask of every CU so that it has a hardware queue of its
+ * own; as streams created with a mask they are blocking streams), which
+ * wait for `stream` and which `stream` then waits for.  STH_EINVAL if a
+ * problem appears twice, STH_ESTATE if one has no coarse guess or a chunked
+ * sweep in progress. */
 int  sth_fine_sweep_batched(sth_problem *const *p, int count, void *stream);
 
 /* The same fine sweep advanced in chunks of at most max_steps fine steps per

@@ -18,9 +18,10 @@
  * All arrays are caller-owned.  Phase-space arrays are x-major: g[p*nv + j].
  *
  * Parity unpinned (no value independent of this oracle exists): the hybrid
- * mask dynamics over long runs, the L = 2 and L = 3 lifting beyond zero mass
- * and its slow-manifold order, and full parareal results at large sizes.
- * Everything else is pinned by tests/test_oracle_pins.py.
+ * mask dynamics over long runs and full parareal results at large sizes.
+ * Everything else is pinned by tests/test_oracle_pins.py and, for the
+ * lifting at orders 2 and 3, by tests/test_lift_recursion.py (the
+ * identification recursion carried out symbolically).
  */
 #ifndef STH_ORACLE_H
 #define STH_ORACLE_H

@@ -80,3 +80,30 @@ def test_traffic_is_read_only_for_the_current_sources(tmp_path, monkeypatch):
     t = bench.measured_traffic("512x64_fp64")
     assert t is not None and t > 0
     assert bench.measured_traffic("no_such_workload") is None
+
+
+def test_batch_traffic_is_read_only_for_the_current_sources(tmp_path, monkeypatch):
+    """The batch counter summary gives (counted bytes, algorithmic bytes) of
+    the first sweep, only when its source hash is that of the kernels run;
+    the counted bytes are the sum of its fetch and write lines."""
+    path = os.path.join(ROOT, "profiles", "k_fine_batch256_fp32_hbm_traffic.txt")
+    if not os.path.exists(path):
+        pytest.skip("no committed batch counter summary")
+    lines = open(path).read().splitlines()
+    kv = dict(l.split(":", 1) for l in lines if ":" in l and not l.startswith("#"))
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "sources_sha256", lambda: "b" * 64)
+    os.makedirs(tmp_path / "profiles")
+    target = tmp_path / "profiles" / "k_fine_batch256_fp32_hbm_traffic.txt"
+
+    def with_sha(h):
+        return "\n".join(f"kernel_sources_sha256: {h}" if l.startswith("kernel_sources_sha256:") else l
+                         for l in lines) + "\n"
+    target.write_text(with_sha("0" * 64))
+    assert bench.measured_batch_traffic() is None
+    target.write_text(with_sha("b" * 64))
+    counted, alg = bench.measured_batch_traffic()
+    assert counted == float(kv["first_sweep_fetch_bytes"]) + float(kv["first_sweep_write_bytes"])
+    assert alg == float(kv["first_sweep_algorithmic_bytes"])
+    assert abs(counted / alg - float(kv["counted_over_algorithmic"])) < 1e-3

@@ -611,10 +611,117 @@ struct LiftBatch {
 };
 
 // Sort the units into kernel classes, stage their table and launch them.
+// Units of several kernel classes in grouped launches: one launch per
+// (precision, workgroup size), every workgroup running the class its unit
+// names, the units of a launch longest first whatever their class, so that
+// the hardware dispatcher starts the slices that bound the sweep first and
+// fills the compute units with the rest behind them.  Classes of at most
+// kFineBlock threads run in kFineBlock-thread workgroups (a small slice then
+// leaves some wavefronts without cells), the wide streamed ones in
+// kWideBlock.
+struct GroupLaunch {
+    int group;                 // precision * 2 + (1 for kWideBlock workgroups)
+    size_t begin, end, lds;    // unit range in the table, LDS bytes
+    double cost;
+};
+
+// The unit table (in launch order, class codes set) and the launches of a
+// grouped sweep; false when some class does not fit a grouped launch.
+bool plan_grouped(const std::vector<SweepItem> &items, std::vector<FineUnit> &table,
+                  std::vector<GroupLaunch> &launches)
+{
+    std::vector<int> grp(items.size());
+    std::vector<size_t> lds(items.size());
+    std::vector<int> code(items.size());
+    for (size_t t = 0; t < items.size(); ++t) {
+        const SweepItem &it = items[t];
+        const bool wide = it.shape.block > kFineBlock;
+        const FineShape g = fine_group_shape(it.shape, it.unit.c.nx, wide ? kWideBlock : kFineBlock);
+        if (g.lds > kMaxLds || (wide && (!g.stream || !fine_wide_ok(g.prec, g.nv)))) return false;
+        grp[t] = it.shape.prec * 2 + (wide ? 1 : 0);
+        lds[t] = g.lds;
+        code[t] = fine_group_code(g);
+    }
+    std::vector<size_t> order(items.size());
+    for (size_t t = 0; t < order.size(); ++t) order[t] = t;
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+        if (grp[a] != grp[b]) return grp[a] < grp[b];
+        return items[a].cost > items[b].cost;
+    });
+    table.resize(items.size());
+    launches.clear();
+    for (size_t t = 0; t < order.size(); ++t) {
+        const size_t u = order[t];
+        table[t] = items[u].unit;
+        table[t].cls = code[u];
+        if (launches.empty() || launches.back().group != grp[u]) launches.push_back({grp[u], t, t, 0, 0.0});
+        GroupLaunch &L = launches.back();
+        L.end = t + 1;
+        L.lds = std::max(L.lds, lds[u]);
+        L.cost += items[u].cost;
+    }
+    return true;
+}
+
+// Issue the launches of a grouped sweep (device table dtab in plan order):
+// one launch on st, or several concurrently on the lanes, costliest first.
+int issue_grouped(std::vector<GroupLaunch> launches, const FineUnit *dtab, hipStream_t st)
+{
+    auto launch = [&](const GroupLaunch &L, hipStream_t s) {
+        return launch_fine_group(L.group / 2, (L.group & 1) ? kWideBlock : kFineBlock, L.lds, dtab + L.begin,
+                                 (int)(L.end - L.begin), s);
+    };
+    if (launches.size() == 1) {
+        HIPCHK(launch(launches[0], st));
+        return STH_OK;
+    }
+    std::stable_sort(launches.begin(), launches.end(),
+                     [](const GroupLaunch &a, const GroupLaunch &b) { return a.cost > b.cost; });
+    SidePool *P = nullptr;
+    int rc = side_pool(&P);
+    if (rc) return rc;
+    // the fork/join events are shared: issue one batch at a time
+    std::lock_guard<std::mutex> lk(g_side_issue_mu);
+    const int nl = std::min<int>(kLanes, (int)launches.size());
+    double load[kLanes] = {};
+    HIPCHK(hipEventRecord(P->fork, st));
+    for (int i = 0; i < nl; ++i) HIPCHK(hipStreamWaitEvent(P->s[i], P->fork, 0));
+    for (const GroupLaunch &L : launches) {
+        int lane = 0;
+        for (int i = 1; i < nl; ++i)
+            if (load[i] < load[lane]) lane = i;
+        load[lane] += L.cost;
+        HIPCHK(launch(L, P->s[lane]));
+    }
+    for (int i = 0; i < nl; ++i) {
+        HIPCHK(hipEventRecord(P->join[i], P->s[i]));
+        HIPCHK(hipStreamWaitEvent(st, P->join[i], 0));
+    }
+    return STH_OK;
+}
+
+bool several_classes(const std::vector<SweepItem> &items)
+{
+    for (size_t t = 1; t < items.size(); ++t)
+        if (!same_class(items[t].shape, items[0].shape)) return true;
+    return false;
+}
+
 int issue_units(std::vector<SweepItem> &items, hipStream_t st)
 {
     if (items.empty()) return STH_OK;
     sort_items(items);
+    std::vector<FineUnit> table;
+    std::vector<GroupLaunch> launches;
+    if (several_classes(items) && plan_grouped(items, table, launches)) {
+        int slot = 0;
+        void *tab = nullptr;
+        int rc = put_table(table.data(), sizeof(FineUnit) * table.size(), st, &slot, &tab);
+        if (rc) return rc;
+        const int rc2 = issue_grouped(launches, (const FineUnit *)tab, st);
+        rc = release_table(slot, st);
+        return rc2 ? rc2 : rc;
+    }
     std::vector<FineUnit> host(items.size());
     for (size_t t = 0; t < items.size(); ++t) host[t] = items[t].unit;
     int slot = 0;
@@ -1062,6 +1169,7 @@ struct GraphOp {
     size_t b;           // COARSE: LDS bytes; LIFT: nx; COPY: largest job (16-byte words)
     size_t items_begin; // FINE: range in the graph's item list
     size_t items_end;
+    int group = -1;     // FINE: index of its grouped plan, or -1 (one launch per class)
 };
 
 struct TableBuilder {
@@ -1108,6 +1216,7 @@ int sth_graph_create(sth_problem *const *probs, int count, sth_graph **out)
     TableBuilder tb;
     std::vector<GraphOp> ops;
     std::vector<SweepItem> all_items;
+    std::vector<std::vector<GroupLaunch>> group_plans;
     auto coarse_op = [&](int mode, int k) {
         std::vector<CoarseJob> jobs;
         int block = kWave;
@@ -1159,10 +1268,17 @@ int sth_graph_create(sth_problem *const *probs, int count, sth_graph **out)
             ops.push_back(op);
         }
         sort_items(items);
-        std::vector<FineUnit> units(items.size());
-        for (size_t t = 0; t < items.size(); ++t) units[t] = items[t].unit;
+        std::vector<FineUnit> units;
+        std::vector<GroupLaunch> gl;
+        const bool grouped = several_classes(items) && plan_grouped(items, units, gl);
+        if (!grouped) {
+            units.resize(items.size());
+            for (size_t t = 0; t < items.size(); ++t) units[t] = items[t].unit;
+        }
         GraphOp op{GraphOp::FINE, tb.put(units.data(), sizeof(FineUnit) * units.size()), (int)units.size(), 0, 0,
                    all_items.size(), all_items.size() + items.size()};
+        op.group = grouped ? (int)group_plans.size() : -1;
+        if (grouped) group_plans.push_back(gl);
         ops.push_back(op);
         all_items.insert(all_items.end(), items.begin(), items.end());
         coarse_op(1, k);
@@ -1189,8 +1305,12 @@ int sth_graph_create(sth_problem *const *probs, int count, sth_graph **out)
             case GraphOp::LIFT: le = launch_lift(op.a, (const LiftJob *)tab, op.n, (int)op.b, g->cap); break;
             case GraphOp::COPY: le = launch_copy((const CopyJob *)tab, op.n, op.b, g->cap); break;
             case GraphOp::FINE: {
-                std::vector<SweepItem> items(all_items.begin() + op.items_begin, all_items.begin() + op.items_end);
-                rc = issue_classes(items, (FineUnit *)tab, g->cap);
+                if (op.group >= 0) {
+                    rc = issue_grouped(group_plans[op.group], (const FineUnit *)tab, g->cap);
+                } else {
+                    std::vector<SweepItem> items(all_items.begin() + op.items_begin, all_items.begin() + op.items_end);
+                    rc = issue_classes(items, (FineUnit *)tab, g->cap);
+                }
                 break;
             }
         }

@@ -74,6 +74,7 @@ struct FineUnit {
     // mask_replay instead of the rule (hybrid runs; NULL in the sweeps).
     const unsigned long long *mask_replay;
     unsigned long long *mask_hist;
+    int cls;                  // class code (fine_class_code) in a grouped launch
 };
 // Checkpoint of a suspended unit: rho, its compensation, Phi, m2 J, the
 // norms, the cell status of the last step and the criterion bits, each nx
@@ -92,6 +93,22 @@ struct FineShape {
 };
 
 FineShape fine_shape(int prec, int nx, int nv, int force_stream, int force_block);
+// Code of a kernel class within one precision and workgroup size: velocity
+// count (16, 32, 64, 128), slabs per thread (1, 2, 4) and row form.
+constexpr int fine_class_code(int nv, int iptm, bool resident)
+{
+    return ((nv == 16 ? 0 : nv == 32 ? 1 : nv == 64 ? 2 : 3) * 3 + (iptm == 1 ? 0 : iptm == 2 ? 1 : 2)) * 2 +
+           (resident ? 1 : 0);
+}
+// Grouped launch: units of several classes of one precision in one launch of
+// `block`-thread workgroups (kFineBlock or kWideBlock), each unit running the
+// class of its code (FineUnit::cls); lds is the largest the units need.
+hipError_t launch_fine_group(int prec, int block, size_t lds, const FineUnit *d_units, int nunits,
+                             hipStream_t st);
+// The shape class s takes in a grouped launch of `block` threads: its row
+// form where that still fits, else streamed; and the code of that shape.
+FineShape fine_group_shape(const FineShape &s, int nx, int block);
+int fine_group_code(const FineShape &g);
 // The streamed kernel of this class exists with kWideBlock threads.
 bool fine_wide_ok(int prec, int nv);
 hipError_t launch_fine(const FineShape &s, const FineUnit *d_units, int nunits, hipStream_t st);

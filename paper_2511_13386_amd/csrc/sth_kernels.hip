@@ -629,7 +629,7 @@ __device__ __forceinline__ RowOut<Real> row_pass_res(Real (&Wr)[NV], const RowCo
 // whose rows fit in the registers of their lanes; otherwise the rows stream
 // from the unit slot every step.
 template <typename Real, int NV, int IPTM, bool RES, int BLK>
-__global__ void __launch_bounds__(BLK) k_fine(const FineUnit *__restrict__ units)
+__device__ __forceinline__ void fine_body(const FineUnit *__restrict__ units)
 {
     constexpr int CH = pair_chunk_len<Real, NV, BLK>();
     constexpr int HV = NV / 2;
@@ -1286,6 +1286,12 @@ __global__ void __launch_bounds__(BLK) k_fine(const FineUnit *__restrict__ units
 #undef HALO
 }
 
+template <typename Real, int NV, int IPTM, bool RES, int BLK>
+__global__ void __launch_bounds__(BLK) k_fine(const FineUnit *__restrict__ units)
+{
+    fine_body<Real, NV, IPTM, RES, BLK>(units);
+}
+
 // Launch shape of a fine-sweep class: one workgroup per unit, up to 1024
 // threads, interfaces distributed over at most kMaxSlabs slabs.
 // Rows of one lane fit its registers in the resident form (at most 128
@@ -1330,6 +1336,23 @@ FineShape fine_shape(int prec, int nx, int nv, int force_stream, int force_block
     return s;
 }
 
+FineShape fine_group_shape(const FineShape &s, int nx, int block)
+{
+    FineShape g = s;
+    const int realsz = s.prec == 0 ? 8 : 4;
+    g.block = block;
+    g.ipt = (nx + block - 1) / block;
+    const int nslot = g.ipt * (block / kWave);
+    const bool res = !s.stream && block <= kFineBlock && g.ipt <= kMaxSlabs &&
+                     fine_resident_fits(realsz, fine_iptm(g.ipt), s.nv) &&
+                     fine_lds(nx, s.nv, realsz, nslot, true).total <= kMaxLds;
+    g.stream = res ? 0 : 1;
+    g.lds = fine_lds(nx, s.nv, realsz, nslot, res).total;
+    return g;
+}
+
+int fine_group_code(const FineShape &g) { return fine_class_code(g.nv, fine_iptm(g.ipt), g.stream == 0); }
+
 template <typename Real, int NV, int IPT, bool RES, int BLK>
 static hipError_t launch_one(const FineShape &s, const FineUnit *d, int n, hipStream_t st)
 {
@@ -1367,6 +1390,63 @@ static hipError_t launch_nv(const FineShape &s, const FineUnit *d, int n, hipStr
         case 3:
         case 4: return launch_form<Real, NV, 4>(s, d, n, st);
     }
+    return hipErrorInvalidValue;
+}
+
+// Grouped fine sweep: every workgroup runs the class its unit names.  The
+// classes of a group share the precision and the workgroup size, so the
+// hardware dispatcher works through one table of units, longest first,
+// whatever their class.  Codes without a kernel of this precision and size
+// are never produced by the host.
+template <typename Real, int BLK, int NV, int IPTM, bool RES>
+__device__ __forceinline__ void fine_group_arm(const FineUnit *__restrict__ units)
+{
+    if constexpr (BLK > kFineBlock) {
+        if constexpr (!RES && IPTM <= 2 && (sizeof(Real) == 4 || NV == 32))
+            fine_body<Real, NV, IPTM, false, BLK>(units);
+    } else if constexpr (!RES || fine_resident_fits((int)sizeof(Real), IPTM, NV)) {
+        fine_body<Real, NV, IPTM, RES, BLK>(units);
+    }
+}
+
+template <typename Real, int BLK>
+__global__ void __launch_bounds__(BLK) k_fine_group(const FineUnit *__restrict__ units)
+{
+    switch (units[blockIdx.x].cls) {
+#define STH_ARM(NV, IPTM, RES)                                   \
+    case fine_class_code(NV, IPTM, RES):                         \
+        fine_group_arm<Real, BLK, NV, IPTM, RES>(units);         \
+        return;
+#define STH_ARMS(NV) STH_ARM(NV, 1, false) STH_ARM(NV, 1, true) STH_ARM(NV, 2, false) \
+                     STH_ARM(NV, 2, true) STH_ARM(NV, 4, false) STH_ARM(NV, 4, true)
+        STH_ARMS(16)
+        STH_ARMS(32)
+        STH_ARMS(64)
+        STH_ARMS(128)
+#undef STH_ARMS
+#undef STH_ARM
+        default:
+            return;
+    }
+}
+
+template <typename Real, int BLK>
+static hipError_t launch_group(size_t lds, const FineUnit *d, int n, hipStream_t st)
+{
+    auto kern = k_fine_group<Real, BLK>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(n), dim3(BLK), lds, st, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_fine_group(int prec, int block, size_t lds, const FineUnit *d, int n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    if (block == kFineBlock) return prec == 0 ? launch_group<double, kFineBlock>(lds, d, n, st)
+                                              : launch_group<float, kFineBlock>(lds, d, n, st);
+    if (block == kWideBlock) return prec == 0 ? launch_group<double, kWideBlock>(lds, d, n, st)
+                                              : launch_group<float, kWideBlock>(lds, d, n, st);
     return hipErrorInvalidValue;
 }
 

@@ -199,29 +199,33 @@ int  sth_coarse_sweep_batched(sth_problem *const *p, int count, void *stream);
 
 /* Fine propagator F = S^HMM (scheme of Section 2.3 with the cell rules of
  * Section 2.2) over every unconverged slice n > k of every problem in the
- * batch, all in one batched launch per kernel class: the parallel loop of
- * Algorithm 1.  Slice-start perturbations follow start_mode.  Asynchronous
- * on `stream`: with several kernel classes the launches run concurrently on
- * four library streams of the current device (created once per process,
- * each with a CU mask of every CU so that it has a hardware queue of its
- * own; as streams created with a mask they are blocking streams), which
- * wait for `stream` and which `stream` then waits for.  STH_EINVAL if a
- * problem appears twice, STH_ESTATE if one has no coarse guess or a chunked
- * sweep in progress. */
+ * batch, one workgroup per slice: the parallel loop of Algorithm 1.
+ * Slice-start perturbations follow start_mode.  One launch when every slice
+ * has the same kernel class (precision, velocity count, interfaces per
+ * thread, row form); a batch that mixes classes is one launch per precision
+ * and workgroup size, each workgroup running the class of its slice, the
+ * longest slices first.  Asynchronous on `stream`: several launches run
+ * concurrently on four library streams of the current device (created once
+ * per process, each with a CU mask of every CU so that it has a hardware
+ * queue of its own; as streams created with a mask they are blocking
+ * streams), which wait for `stream` and which `stream` then waits for.
+ * STH_EINVAL if a problem appears twice, STH_ESTATE if one has no coarse
+ * guess or a chunked sweep in progress. */
 int  sth_fine_sweep_batched(sth_problem *const *p, int count, void *stream);
 
 /* The same fine sweep advanced in chunks of at most max_steps fine steps per
  * slice, so that a caller can interleave other work between chunks (the
  * serving loop batches solves per chunk).  A call starts the sweep of every
  * problem that has none in progress (slice starts as above), then runs the
- * next chunk of steps of every slice of every problem in one launch per
- * kernel class; a suspended slice keeps its state in the problem's memory
- * (its rows, lazy projection and halos in the slice's slot, its
- * macroscopic state in a checkpoint).  done_out[count] (optional) receives
- * 1 for each problem whose sweep has ended (in this call or an earlier one)
- * and awaits its correction; such problems are not swept again.  The results equal those of sth_fine_sweep_batched bit
- * for bit, whatever the chunk lengths.  sth_fine_sweep_batched refuses a
- * problem with a chunked sweep in progress (STH_ESTATE). */
+ * next chunk of steps of every slice of every problem, launched as
+ * sth_fine_sweep_batched launches; a suspended slice keeps its state in
+ * the problem's memory (its rows, lazy projection and halos in the slice's
+ * slot, its macroscopic state in a checkpoint).  done_out[count] (optional)
+ * receives 1 for each problem whose sweep has ended (in this call or an
+ * earlier one) and awaits its correction; such problems are not swept
+ * again.  The results equal those of sth_fine_sweep_batched bit for bit,
+ * whatever the chunk lengths.  sth_fine_sweep_batched refuses a problem
+ * with a chunked sweep in progress (STH_ESTATE). */
 int  sth_fine_sweep_chunk(sth_problem *const *p, int count, long long max_steps, int *done_out, void *stream);
 
 /* Sequential correction of Algorithm 1 with the new coarse value:

@@ -636,3 +636,43 @@ def test_config4_fp32_bulk_with_adaptation(orc):
         assert rel_err(r2, ro) < rt and rel_err(g2, go) < gt, (inst.nx, inst.nv)
     for p in ps:
         p.close()
+
+
+def test_grouped_launch_small_slices_both_row_forms():
+    """A batch that mixes kernel classes runs as grouped launches (one per
+    precision and workgroup size, 512 threads even for slices of fewer
+    interfaces); each problem equals, bit for bit, the same problem swept
+    alone by its own class kernel in its own workgroup size: small slices
+    in both row forms (one forced streamed), a wide streamed class, and an
+    FP64 class beside FP32 ones."""
+    cases = [
+        (wl.random_instance(21, N=3, T=1e-3, nx_choices=(96,), nv_choices=(32,)), sth.FP32_BULK, (128, 0)),
+        (wl.random_instance(22, N=3, T=1e-3, nx_choices=(200,), nv_choices=(64,)), sth.FP32_BULK, None),
+        (wl.random_instance(23, N=2, T=1e-3, nx_choices=(1100,), nv_choices=(128,)), sth.FP32_BULK, None),
+        (wl.random_instance(24, N=4, T=1e-3, nx_choices=(64,), nv_choices=(16,)), sth.FP32_BULK, None),
+        (wl.random_instance(25, N=3, T=1e-3, nx_choices=(130,), nv_choices=(64,)), sth.FP64, (192, 0)),
+    ]
+    for inst, prec, cfg in cases:
+        if cfg is not None:
+            assert cfg in sth.sth_fine_config_candidates(prec, inst.nx, inst.nv)
+            sth.sth_set_fine_config(prec, inst.nx, inst.nv, cfg)
+    try:
+        alone = []
+        for inst, prec, _ in cases:
+            q = sth.Problem(desc_of(inst, precision=prec, K=2))
+            sth.parareal_solve(q, K=2, fixed_iterations=True)
+            alone.append((sth.sth_get_rho(q), sth.sth_get_g(q, q.N)))
+            q.close()
+        mix = [sth.Problem(desc_of(inst, precision=prec, K=2)) for inst, prec, _ in cases]
+        sth.sth_coarse_sweep_batched(mix)
+        for _ in range(2):
+            sth.sth_fine_sweep_batched(mix)
+            sth.sth_parareal_correct_batched(mix, want_err=False)
+        for q, (ua, ga) in zip(mix, alone):
+            assert np.array_equal(sth.sth_get_rho(q), ua), (q.nx, q.nv)
+            assert np.array_equal(sth.sth_get_g(q, q.N), ga), (q.nx, q.nv)
+            q.close()
+    finally:
+        for inst, prec, cfg in cases:
+            if cfg is not None:
+                sth.sth_set_fine_config(prec, inst.nx, inst.nv, None)

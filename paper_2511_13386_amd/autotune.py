@@ -10,6 +10,10 @@ as many slices as the workload has units of it (so that occupancy is that
 of the real sweep), times a short batched sweep under every supported
 configuration (`sth_fine_config_candidates`) and keeps the fastest
 (`sth_set_fine_config`).  Results can be saved to and loaded from JSON.
+A sweep of one class runs the chosen configuration as it is; a batch that
+mixes classes runs grouped launches, where a class keeps its row form and
+its choice between the 1024-thread streamed form and the others, and takes
+the group's workgroup size.
 
 Host-side orchestration only: the timed work is the library's own sweep.
 """
